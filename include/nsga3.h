@@ -1,0 +1,157 @@
+/*
+ * nsga3.h -- NSGA-III environmental selection on one AMD Instinct MI355X (gfx950).
+ *
+ * The library computes the environmental selection of NSGA-III on a merged
+ * population: Pareto-dominance counts and nondominated fronts, ideal/extreme
+ * point normalisation, association of every admitted point with its closest
+ * reference line, niche counts, and the niche-preserving pick from the last
+ * admitted front.
+ *
+ * Paper: Liang, Li, Yu, Sun, Cheng, "Bridging Evolutionary Multiobjective
+ * Optimization and GPU Acceleration via Tensorization", IEEE TEVC 2025.
+ *   - selection as a whole: Sec. IV-A; Alg. S.1 (original) and Alg. S.4 (tensorized)
+ *   - dominance: Listing 1, Eq. (6); dominance count: Eq. (7)
+ *   - fronts: Eq. (8)-(9), Alg. S.3; last front l: end of Sec. IV-A.1
+ *   - normalisation: Alg. S.5;  association: Eq. (10);  niche counts: Eq. (11)
+ *   - niching: Alg. S.1 (its inner loop);  output indices: Eq. (13)
+ *
+ * Conventions shared by all entry points
+ *   - All objectives are minimised (Eq. (1)).  Objective matrices are N x M,
+ *     row-major float32; reference matrices are H x M, row-major float32 with
+ *     non-negative entries and a non-zero norm per row.
+ *   - Pointers marked DEVICE are device memory on the context's device; every
+ *     other pointer is host memory.  The caller owns every buffer it passes;
+ *     the context owns its workspace.
+ *   - Calls that take a stream are asynchronous and stream-ordered: outputs are
+ *     valid once the stream has been synchronised.  No call synchronises the
+ *     stream or the device unless stated.
+ *   - Errors that can be checked on the host are returned immediately and
+ *     nothing is enqueued.  Errors that need the data (non-finite values, a bad
+ *     reference row) are reported through nsga3_info.status on the device; the
+ *     outputs of such a call are then undefined.
+ *   - A context is not thread-safe: use one context per host thread.  A context
+ *     stays usable after any error.
+ */
+#ifndef NSGA3_H
+#define NSGA3_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NSGA3_OK = 0,
+    NSGA3_E_INVALID = -1,      /* bad argument (null pointer, size out of range) */
+    NSGA3_E_NONFINITE = -2,    /* NaN/Inf objective, or invalid reference row (device-side) */
+    NSGA3_E_NOMEM = -3,        /* workspace allocation failed or exceeds the configured cap */
+    NSGA3_E_HIP = -4,          /* a HIP runtime call failed */
+    NSGA3_E_UNSUPPORTED = -5   /* device is not gfx950, or cooperative launch unavailable */
+} nsga3_status;
+
+typedef enum {
+    NSGA3_ASSOC_FP32 = 0,      /* candidate screening in float32 on the vector ALUs */
+    NSGA3_ASSOC_BF16 = 1       /* candidate screening in bfloat16 on the matrix cores */
+} nsga3_assoc_mode;
+
+typedef struct {
+    nsga3_assoc_mode assoc;       /* default NSGA3_ASSOC_FP32 */
+    int32_t reserved0;
+    size_t max_workspace_bytes;   /* 0 = no cap */
+} nsga3_options;
+
+/* Per-call diagnostics, written on-stream into DEVICE memory. */
+typedef struct {
+    int32_t status;               /* NSGA3_OK or NSGA3_E_NONFINITE */
+    int32_t last_front;           /* l: rank of the K-th smallest rank (0-based) */
+    int32_t num_fronts;           /* L: number of nondominated fronts */
+    int32_t last_front_size;      /* |F_l| */
+    int32_t num_from_last;        /* R = K - #{rank < l}: members picked from F_l */
+    int32_t intercept_fallback;   /* 0 hyperplane, 1 nadir, 2 nadir with a zero axis set to 1 */
+    int32_t near_ties;            /* admitted points whose two closest reference lines are
+                                     within 1e-6 relative distance (float64 re-scoring) */
+    int32_t reserved;
+} nsga3_info;
+
+typedef struct nsga3_ctx nsga3_ctx;
+
+/* Create a context on HIP device `device` (must be gfx950).  `opt` may be NULL
+ * for the defaults.  On success *out receives the context. */
+nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt);
+
+/* Destroy a context and free its workspace.  Waits for nothing: the caller must
+ * make sure no work using the context is still running.  NULL is ignored. */
+void nsga3_destroy(nsga3_ctx *ctx);
+
+/* Grow the context's workspace so that later calls with N <= N_max, M <= M_max,
+ * H <= H_max allocate nothing.  Synchronous (allocation).  Sizes are checked as
+ * in nsga3_select. */
+nsga3_status nsga3_reserve(nsga3_ctx *ctx, int64_t N_max, int32_t M_max, int32_t H_max);
+
+/* Bytes of workspace a call of this size needs (host-only query). */
+nsga3_status nsga3_workspace_size(int64_t N, int32_t M, int32_t H, size_t *bytes);
+
+/*
+ * Environmental selection of K out of N points (Alg. S.1 / Alg. S.4).
+ *
+ *   objs      DEVICE float[N*M]  objective values, row-major, minimised
+ *   N         1 <= N <= 2^31-1   merged population size
+ *   M         2 <= M <= 16       number of objectives
+ *   refs      DEVICE float[H*M]  reference directions (rows >= 0, non-zero norm)
+ *   H         1 <= H <= 65535    number of reference directions
+ *   K         1 <= K <= N        number of points to select
+ *   selected  DEVICE int32[K]    required: selected point indices, ascending (Eq. (13))
+ *   rank      DEVICE int32[N]    optional: 0-based front index of every point (Eq. (8)-(9))
+ *   niche     DEVICE int32[N]    optional: closest reference line for rank <= l, else -1 (Eq. (10))
+ *   dist      DEVICE float[N]    optional: perpendicular distance to it (normalised
+ *                                objective space, Alg. S.5), else -1
+ *   dom_in    DEVICE int32[N]    optional: number of points dominating each point (Eq. (7))
+ *   dom_out   DEVICE int32[N]    optional: number of points each point dominates
+ *   info      DEVICE nsga3_info* optional: diagnostics (see nsga3_info)
+ *   stream    HIP stream to enqueue on (0 = legacy default stream)
+ *
+ * Determinism: every output is a function of the inputs only (no dependence on
+ * scheduling).  Ties are resolved by lowest index everywhere; the "random"
+ * member of a crowded niche (Alg. S.1) is its closest remaining member.
+ * Workspace grows on demand (synchronous allocation) unless nsga3_reserve was
+ * called with sufficient sizes.
+ */
+nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t M,
+                          const float *refs, int32_t H, int64_t K,
+                          int32_t *selected, int32_t *rank, int32_t *niche, float *dist,
+                          int32_t *dom_in, int32_t *dom_out, nsga3_info *info,
+                          hipStream_t stream);
+
+/* Phases of one nsga3_select call, for nsga3_phase_times. */
+#define NSGA3_NUM_PHASES 6
+/*   0  keys, ideal point, presort by key sum            (Alg. S.5 first step; sort prerequisite)
+ *   1  dominance counts over all pairs                  (Listing 1, Eq. (6)-(7))
+ *   2  front peeling and last front                     (Eq. (8)-(9), Alg. S.3)
+ *   3  extreme points and intercepts                    (Alg. S.5)
+ *   4  association and niche counts                     (Eq. (10)-(12))
+ *   5  niche-preserving pick and output compaction      (Alg. S.1, Eq. (13)) */
+
+/* Enable (1) or disable (0) phase timing.  While enabled, every nsga3_select
+ * records NSGA3_NUM_PHASES + 1 HIP events on its stream (event creation may
+ * allocate on the first calls).  Enabling clears the accumulated times. */
+nsga3_status nsga3_profile(nsga3_ctx *ctx, int enable);
+
+/* Synchronises on the recorded events and returns, per phase, the summed
+ * duration in milliseconds over all calls since profiling was enabled
+ * (ms: host double[NSGA3_NUM_PHASES]; calls: host, may be NULL), then clears. */
+nsga3_status nsga3_phase_times(nsga3_ctx *ctx, double *ms, int64_t *calls);
+
+/* Human-readable name of a status code (static string). */
+const char *nsga3_status_string(nsga3_status s);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t nsga3_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NSGA3_H */

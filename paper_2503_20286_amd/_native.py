@@ -1,0 +1,250 @@
+"""ctypes marshalling for libnsga3.so.  No computation happens here."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import threading
+from dataclasses import dataclass
+from typing import Dict, Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+HEADER = os.path.join(ROOT, "include", "nsga3.h")
+
+
+def lib_path() -> str:
+    return os.environ.get("NSGA3_LIB", os.path.join(HERE, "libnsga3.so"))
+
+
+STATUS = {0: "NSGA3_OK", -1: "NSGA3_E_INVALID", -2: "NSGA3_E_NONFINITE", -3: "NSGA3_E_NOMEM",
+          -4: "NSGA3_E_HIP", -5: "NSGA3_E_UNSUPPORTED"}
+NUM_PHASES = 6
+PHASES = ("prep_sort", "dominance_count", "peel", "normalize", "associate", "niching")
+ASSOC_FP32 = 0
+ASSOC_BF16 = 1
+
+
+class NativeError(RuntimeError):
+    def __init__(self, what: str, code: int, lib=None):
+        msg = STATUS.get(code, str(code))
+        if lib is not None:
+            try:
+                msg += ": " + lib.nsga3_status_string(code).decode()
+            except Exception:  # pragma: no cover - best effort
+                pass
+        super().__init__(f"{what} failed ({msg})")
+        self.code = code
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("assoc", ctypes.c_int), ("reserved0", ctypes.c_int32),
+                ("max_workspace_bytes", ctypes.c_size_t)]
+
+
+INFO_FIELDS = ("status", "last_front", "num_fronts", "last_front_size", "num_from_last",
+               "intercept_fallback", "near_ties", "reserved")
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load():
+    """Load libnsga3.so (built by paper_2503_20286_amd.build); raise if absent."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        path = lib_path()
+        if not os.path.exists(path):
+            raise ImportError(f"libnsga3.so not found at {path}: build it first "
+                              "(python -m paper_2503_20286_amd.build or __graft_entry__.build())")
+        L = ctypes.CDLL(path)
+        P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.nsga3_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(_Options)]
+        L.nsga3_create.restype = ctypes.c_int
+        L.nsga3_destroy.argtypes = [P]
+        L.nsga3_destroy.restype = None
+        L.nsga3_reserve.argtypes = [P, i64, i32, i32]
+        L.nsga3_reserve.restype = ctypes.c_int
+        L.nsga3_workspace_size.argtypes = [i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.nsga3_workspace_size.restype = ctypes.c_int
+        L.nsga3_select.argtypes = [P, P, i64, i32, P, i32, i64, P, P, P, P, P, P, P, P]
+        L.nsga3_select.restype = ctypes.c_int
+        L.nsga3_status_string.argtypes = [ctypes.c_int]
+        L.nsga3_status_string.restype = ctypes.c_char_p
+        L.nsga3_profile.argtypes = [P, ctypes.c_int]
+        L.nsga3_profile.restype = ctypes.c_int
+        L.nsga3_phase_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+        L.nsga3_phase_times.restype = ctypes.c_int
+        L.nsga3_version.argtypes = []
+        L.nsga3_version.restype = ctypes.c_int32
+        _lib = L
+        return L
+
+
+def version() -> int:
+    return int(load().nsga3_version())
+
+
+def header_symbols():
+    """Function names declared by include/nsga3.h."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nsga3_[a-z_]+)\s*\(", text)))
+
+
+def exported_symbols():
+    """Which header-declared functions the shared library exports (name -> bool)."""
+    L = load()
+    out = {}
+    for name in header_symbols():
+        try:
+            getattr(L, name)
+            out[name] = True
+        except AttributeError:
+            out[name] = False
+    return out
+
+
+class Context:
+    """Owns an nsga3_ctx (device workspace) on one HIP device."""
+
+    def __init__(self, device: int = 0, assoc: int = ASSOC_FP32, max_workspace_bytes: int = 0):
+        self._lib = load()
+        opt = _Options(assoc, 0, max_workspace_bytes)
+        h = ctypes.c_void_p()
+        rc = self._lib.nsga3_create(ctypes.byref(h), int(device), ctypes.byref(opt))
+        if rc != 0:
+            raise NativeError("nsga3_create", rc, self._lib)
+        self._h = h
+        self.device = int(device)
+        self.assoc = assoc
+
+    @property
+    def handle(self):
+        return self._h
+
+    def reserve(self, N: int, M: int, H: int) -> None:
+        rc = self._lib.nsga3_reserve(self._h, int(N), int(M), int(H))
+        if rc != 0:
+            raise NativeError("nsga3_reserve", rc, self._lib)
+
+    def profile(self, enable: bool) -> None:
+        rc = self._lib.nsga3_profile(self._h, 1 if enable else 0)
+        if rc != 0:
+            raise NativeError("nsga3_profile", rc, self._lib)
+
+    def phase_times(self):
+        """(per-phase summed milliseconds, number of calls) since profiling was enabled."""
+        ms = (ctypes.c_double * NUM_PHASES)()
+        calls = ctypes.c_int64()
+        rc = self._lib.nsga3_phase_times(self._h, ms, ctypes.byref(calls))
+        if rc != 0:
+            raise NativeError("nsga3_phase_times", rc, self._lib)
+        return [float(x) for x in ms], int(calls.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.nsga3_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx: Dict[tuple, Context] = {}
+
+
+def default_context(device: int, assoc: int = ASSOC_FP32) -> Context:
+    key = (device, assoc)
+    if key not in _default_ctx:
+        _default_ctx[key] = Context(device, assoc)
+    return _default_ctx[key]
+
+
+@dataclass
+class Info:
+    status: int
+    last_front: int
+    num_fronts: int
+    last_front_size: int
+    num_from_last: int
+    intercept_fallback: int
+    near_ties: int
+    device_err_bits: int
+
+
+@dataclass
+class Selection:
+    selected: "object"
+    rank: "object"
+    niche: "object"
+    dist: "object"
+    dom_in: "object"
+    dom_out: "object"
+    info_raw: "object"
+
+    def info(self) -> Info:
+        """Copies the device-side nsga3_info to the host (synchronises)."""
+        v = [int(x) for x in self.info_raw.cpu().tolist()]
+        return Info(*v)
+
+
+def _check_tensor(t, name, ndim):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on a HIP device")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if t.dim() != ndim or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {ndim}-D tensor")
+
+
+def select(objs, refs, K: int, *, ctx: Optional[Context] = None, assoc: int = ASSOC_FP32,
+           want_counts: bool = True, want_dist: bool = True, out: Optional[Selection] = None,
+           stream=None) -> Selection:
+    """Environmental selection of K of the N rows of ``objs`` (N x M float32,
+    minimised) with reference directions ``refs`` (H x M float32).  Returns
+    device tensors; the call is asynchronous on the current (or given) stream."""
+    import torch
+    _check_tensor(objs, "objs", 2)
+    _check_tensor(refs, "refs", 2)
+    if objs.device != refs.device:
+        raise ValueError("objs and refs must be on the same device")
+    N, M = objs.shape
+    H = refs.shape[0]
+    if refs.shape[1] != M:
+        raise ValueError("refs must have M columns")
+    dev = objs.device
+    if ctx is None:
+        ctx = default_context(dev.index if dev.index is not None else torch.cuda.current_device(), assoc)
+    if out is None:
+        i32 = dict(dtype=torch.int32, device=dev)
+        out = Selection(
+            selected=torch.empty(int(K), **i32) if K >= 1 else torch.empty(1, **i32),
+            rank=torch.empty(N, **i32),
+            niche=torch.empty(N, **i32),
+            dist=torch.empty(N, dtype=torch.float32, device=dev) if want_dist else None,
+            dom_in=torch.empty(N, **i32) if want_counts else None,
+            dom_out=torch.empty(N, **i32) if want_counts else None,
+            info_raw=torch.zeros(8, **i32),
+        )
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+
+    def p(t):
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+    rc = ctx._lib.nsga3_select(ctx.handle, p(objs), int(N), int(M), p(refs), int(H), int(K),
+                               p(out.selected), p(out.rank), p(out.niche), p(out.dist),
+                               p(out.dom_in), p(out.dom_out), p(out.info_raw),
+                               ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise NativeError("nsga3_select", rc, ctx._lib)
+    return out

@@ -1,0 +1,362 @@
+// C ABI of libnsga3: context, workspace and the environmental-selection entry
+// point.  Host code only; the kernels live in dominance.hip, select.hip and
+// sort_scan.hip.
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace nsga3;
+
+struct nsga3_ctx {
+    int device;
+    nsga3_options opt;
+    int num_cus;
+    int peel_bpc[17];
+    void *ws;
+    size_t ws_bytes;
+    bool profiling;
+    std::vector<hipEvent_t> ev_pool;   // NSGA3_NUM_PHASES + 1 events per recorded call
+    size_t ev_used;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxPeelBlocksPerCu = 2;
+
+struct Layout {
+    size_t skey, skey_alt, sval, sval_alt, temp, recs, runstart, dom_in_s, dom_out_s, rank_s;
+    size_t fk0, fk1, uk0, uk1, urun0, urun1, ucnt0, ucnt1, fsize, blkcnt;
+    size_t rank, niche, dist64, rhat64, rhat32, p_asf, p_idx, p_nad;
+    size_t rho, bcount, bstart, bcursor, bd, bi, selflag, sc;
+    size_t total;
+};
+
+size_t bump(size_t &cur, size_t bytes) {
+    const size_t at = cur;
+    cur += (bytes + kAlign - 1) / kAlign * kAlign;
+    return at;
+}
+
+Layout layout_for(int64_t N, int M, int H, int max_grid) {
+    Layout L;
+    size_t c = 0;
+    const size_t n = (size_t)N;
+    const size_t MP = (size_t)rec_stride(M);
+    size_t temp = radix_sort_temp_bytes(N);
+    const size_t ct = compact_temp_bytes(N);
+    if (ct > temp) temp = ct;
+    const int nparts = normalize_partial_blocks(N);
+    L.skey = bump(c, 8 * n);
+    L.skey_alt = bump(c, 8 * n);
+    L.sval = bump(c, 4 * n);
+    L.sval_alt = bump(c, 4 * n);
+    L.temp = bump(c, temp);
+    L.recs = bump(c, 4 * n * MP);
+    L.runstart = bump(c, 4 * n);
+    L.dom_in_s = bump(c, 4 * n);
+    L.dom_out_s = bump(c, 4 * n);
+    L.rank_s = bump(c, 4 * n);
+    L.fk0 = bump(c, 4 * n * MP);
+    L.fk1 = bump(c, 4 * n * MP);
+    L.uk0 = bump(c, 4 * n * MP);
+    L.uk1 = bump(c, 4 * n * MP);
+    L.urun0 = bump(c, 4 * n);
+    L.urun1 = bump(c, 4 * n);
+    L.ucnt0 = bump(c, 4 * n);
+    L.ucnt1 = bump(c, 4 * n);
+    L.fsize = bump(c, 4 * n);
+    L.blkcnt = bump(c, 8 * (size_t)max_grid);
+    L.rank = bump(c, 4 * n);
+    L.niche = bump(c, 4 * n);
+    L.dist64 = bump(c, 8 * n);
+    L.rhat64 = bump(c, 8 * (size_t)H * M);
+    L.rhat32 = bump(c, 4 * (size_t)H * M);
+    L.p_asf = bump(c, 8 * (size_t)nparts * M);
+    L.p_idx = bump(c, 4 * (size_t)nparts * M);
+    L.p_nad = bump(c, 8 * (size_t)nparts * M);
+    L.rho = bump(c, 4 * (size_t)H);
+    L.bcount = bump(c, 4 * (size_t)H);
+    L.bstart = bump(c, 4 * ((size_t)H + 1));
+    L.bcursor = bump(c, 4 * (size_t)H);
+    L.bd = bump(c, 8 * n);
+    L.bi = bump(c, 4 * n);
+    L.selflag = bump(c, n);
+    L.sc = bump(c, sizeof(DevScalars));
+    L.total = c;
+    return L;
+}
+
+bool sizes_ok(int64_t N, int32_t M, int32_t H) {
+    return N >= 1 && N <= 2147483647LL && M >= 2 && M <= 16 && H >= 1 && H <= 65535;
+}
+
+// Workspace sizes grow monotonically in N, M and H, so the layout for the
+// largest request fits every smaller one.
+const int kGridCap = 256 * 16;
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            changed = hipSetDevice(dev) == hipSuccess;
+        }
+    }
+    ~DeviceGuard() {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+nsga3_status ensure_ws(nsga3_ctx *ctx, size_t need) {
+    if (need <= ctx->ws_bytes) return NSGA3_OK;
+    if (ctx->opt.max_workspace_bytes && need > ctx->opt.max_workspace_bytes) return NSGA3_E_NOMEM;
+    if (getenv("NSGA3_TEST_FAIL_ALLOC")) return NSGA3_E_NOMEM;
+    if (ctx->ws) {
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return NSGA3_E_NOMEM;
+    }
+    ctx->ws = p;
+    ctx->ws_bytes = need;
+    return NSGA3_OK;
+}
+
+// Phase boundary marker: records the next pooled event when profiling.
+struct PhaseMarks {
+    nsga3_ctx *ctx;
+    hipStream_t s;
+    bool on;
+    PhaseMarks(nsga3_ctx *c, hipStream_t st) : ctx(c), s(st), on(c->profiling) {
+        if (on && c->ev_used + NSGA3_NUM_PHASES + 1 > c->ev_pool.size()) {
+            for (int q = 0; q <= NSGA3_NUM_PHASES; ++q) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+                c->ev_pool.push_back(e);
+            }
+        }
+    }
+    void mark() {
+        if (on) (void)hipEventRecord(ctx->ev_pool[ctx->ev_used++], s);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *nsga3_status_string(nsga3_status s) {
+    switch (s) {
+        case NSGA3_OK: return "ok";
+        case NSGA3_E_INVALID: return "invalid argument";
+        case NSGA3_E_NONFINITE: return "non-finite objective or invalid reference direction";
+        case NSGA3_E_NOMEM: return "out of device memory or over the workspace cap";
+        case NSGA3_E_HIP: return "HIP runtime error";
+        case NSGA3_E_UNSUPPORTED: return "unsupported device or launch mode";
+    }
+    return "unknown status";
+}
+
+int32_t nsga3_version(void) { return 100; }
+
+nsga3_status nsga3_workspace_size(int64_t N, int32_t M, int32_t H, size_t *bytes) {
+    if (!bytes || !sizes_ok(N, M, H)) return NSGA3_E_INVALID;
+    *bytes = layout_for(N, M, H, kGridCap).total;
+    return NSGA3_OK;
+}
+
+nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt) {
+    if (!out) return NSGA3_E_INVALID;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) { (void)hipGetLastError(); return NSGA3_E_HIP; }
+    if (device < 0 || device >= ndev) return NSGA3_E_INVALID;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return NSGA3_E_HIP;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return NSGA3_E_UNSUPPORTED;
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop)
+        return NSGA3_E_UNSUPPORTED;
+    nsga3_ctx *c = new (std::nothrow) nsga3_ctx();
+    if (!c) return NSGA3_E_NOMEM;
+    c->device = device;
+    c->opt.assoc = NSGA3_ASSOC_FP32;
+    c->opt.reserved0 = 0;
+    c->opt.max_workspace_bytes = 0;
+    if (opt) c->opt = *opt;
+    if (c->opt.assoc != NSGA3_ASSOC_FP32 && c->opt.assoc != NSGA3_ASSOC_BF16) {
+        delete c;
+        return NSGA3_E_INVALID;
+    }
+    c->num_cus = prop.multiProcessorCount;
+    DeviceGuard g(device);
+    for (int m = 0; m <= 16; ++m) c->peel_bpc[m] = 0;
+    for (int m = 2; m <= 16; ++m) {
+        int nb = peel_max_blocks_per_cu(m);
+        c->peel_bpc[m] = nb < kMaxPeelBlocksPerCu ? nb : kMaxPeelBlocksPerCu;
+        if (c->peel_bpc[m] < 1 || c->num_cus * c->peel_bpc[m] > kGridCap) {
+            delete c;
+            return NSGA3_E_UNSUPPORTED;
+        }
+    }
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    c->profiling = false;
+    c->ev_used = 0;
+    *out = c;
+    return NSGA3_OK;
+}
+
+void nsga3_destroy(nsga3_ctx *ctx) {
+    if (!ctx) return;
+    {
+        DeviceGuard g(ctx->device);
+        if (ctx->ws) (void)hipFree(ctx->ws);
+        for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    }
+    delete ctx;
+}
+
+nsga3_status nsga3_profile(nsga3_ctx *ctx, int enable) {
+    if (!ctx) return NSGA3_E_INVALID;
+    ctx->profiling = enable != 0;
+    ctx->ev_used = 0;
+    return NSGA3_OK;
+}
+
+nsga3_status nsga3_phase_times(nsga3_ctx *ctx, double *ms, int64_t *calls) {
+    if (!ctx || !ms) return NSGA3_E_INVALID;
+    DeviceGuard g(ctx->device);
+    for (int q = 0; q < NSGA3_NUM_PHASES; ++q) ms[q] = 0.0;
+    const size_t per = NSGA3_NUM_PHASES + 1;
+    const size_t n = ctx->ev_used / per;
+    for (size_t c = 0; c < n; ++c) {
+        hipEvent_t *e = &ctx->ev_pool[c * per];
+        if (hipEventSynchronize(e[NSGA3_NUM_PHASES]) != hipSuccess) return NSGA3_E_HIP;
+        for (int q = 0; q < NSGA3_NUM_PHASES; ++q) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, e[q], e[q + 1]) != hipSuccess) return NSGA3_E_HIP;
+            ms[q] += (double)t;
+        }
+    }
+    if (calls) *calls = (int64_t)n;
+    ctx->ev_used = 0;
+    return NSGA3_OK;
+}
+
+nsga3_status nsga3_reserve(nsga3_ctx *ctx, int64_t N_max, int32_t M_max, int32_t H_max) {
+    if (!ctx || !sizes_ok(N_max, M_max, H_max)) return NSGA3_E_INVALID;
+    DeviceGuard g(ctx->device);
+    return ensure_ws(ctx, layout_for(N_max, M_max, H_max, kGridCap).total);
+}
+
+nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t M,
+                          const float *refs, int32_t H, int64_t K, int32_t *selected, int32_t *rank,
+                          int32_t *niche, float *dist, int32_t *dom_in, int32_t *dom_out,
+                          nsga3_info *info, hipStream_t stream) {
+    if (!ctx || !objs || !refs || !selected) return NSGA3_E_INVALID;
+    if (!sizes_ok(N, M, H) || K < 1 || K > N) return NSGA3_E_INVALID;
+    DeviceGuard g(ctx->device);
+    const Layout L = layout_for(N, M, H, kGridCap);
+    nsga3_status st = ensure_ws(ctx, L.total);
+    if (st != NSGA3_OK) return st;
+    char *w = (char *)ctx->ws;
+#define WS(T, f) reinterpret_cast<T *>(w + L.f)
+    DevScalars *sc = WS(DevScalars, sc);
+    int32_t *rank_o = rank ? rank : WS(int32_t, rank);
+    int32_t *niche_o = niche ? niche : WS(int32_t, niche);
+
+    PhaseMarks marks(ctx, stream);
+    Marker mk;
+    mk.fn = [](void *a) { static_cast<PhaseMarks *>(a)->mark(); };
+    mk.arg = &marks;
+    marks.mark();
+    int32_t *zero_p[] = {WS(int32_t, dom_in_s), WS(int32_t, dom_out_s), WS(int32_t, rho),
+                         WS(int32_t, bcount)};
+    const int64_t zero_n[] = {N, N, H, H};
+    hipError_t e = run_init(sc, zero_p, zero_n, 4, stream);
+    if (e == hipSuccess) e = run_refs(refs, H, M, WS(double, rhat64), WS(float, rhat32), sc, stream);
+
+    SortViews sv;
+    sv.objs = objs;
+    sv.N = N;
+    sv.M = M;
+    sv.K = K;
+    sv.skey = WS(uint64_t, skey);
+    sv.skey_alt = WS(uint64_t, skey_alt);
+    sv.sval = WS(uint32_t, sval);
+    sv.sval_alt = WS(uint32_t, sval_alt);
+    sv.temp = WS(uint32_t, temp);
+    sv.recs = WS(uint32_t, recs);
+    sv.runstart = WS(int32_t, runstart);
+    sv.dom_in_s = WS(int32_t, dom_in_s);
+    sv.dom_out_s = WS(int32_t, dom_out_s);
+    sv.rank_s = WS(int32_t, rank_s);
+    sv.fk[0] = WS(uint32_t, fk0);
+    sv.fk[1] = WS(uint32_t, fk1);
+    sv.uk[0] = WS(uint32_t, uk0);
+    sv.uk[1] = WS(uint32_t, uk1);
+    sv.urun[0] = WS(int32_t, urun0);
+    sv.urun[1] = WS(int32_t, urun1);
+    sv.ucnt[0] = WS(int32_t, ucnt0);
+    sv.ucnt[1] = WS(int32_t, ucnt1);
+    sv.fsize = WS(int32_t, fsize);
+    sv.blkcnt = WS(uint32_t, blkcnt);
+    sv.rank = rank_o;
+    sv.dom_in = dom_in;
+    sv.dom_out = dom_out;
+    sv.sc = sc;
+    sv.mark = mk;
+    LaunchCfg cfg;
+    cfg.num_cus = ctx->num_cus;
+    cfg.peel_blocks_per_cu = ctx->peel_bpc[M];
+    if (e == hipSuccess) e = run_sort_stage(sv, cfg, stream);
+
+    SelectViews xv;
+    xv.objs = objs;
+    xv.N = N;
+    xv.M = M;
+    xv.refs = refs;
+    xv.H = H;
+    xv.K = K;
+    xv.rank = rank_o;
+    xv.niche = niche_o;
+    xv.dist = dist;
+    xv.dist64 = WS(double, dist64);
+    xv.rhat64 = WS(double, rhat64);
+    xv.rhat32 = WS(float, rhat32);
+    xv.p_asf = WS(double, p_asf);
+    xv.p_idx = WS(int32_t, p_idx);
+    xv.p_nad = WS(double, p_nad);
+    xv.rho = WS(int32_t, rho);
+    xv.bcount = WS(int32_t, bcount);
+    xv.bstart = WS(int32_t, bstart);
+    xv.bcursor = WS(int32_t, bcursor);
+    xv.bd = WS(double, bd);
+    xv.bi = WS(int32_t, bi);
+    xv.selflag = WS(uint8_t, selflag);
+    xv.temp = WS(uint32_t, temp);
+    xv.selected = selected;
+    xv.info = info;
+    xv.sc = sc;
+    xv.assoc_mode = (int)ctx->opt.assoc;
+    xv.mark = mk;
+#undef WS
+    if (e == hipSuccess) e = run_select_stage(xv, stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return NSGA3_E_HIP;
+    }
+    return NSGA3_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Host-side launchers for the libnsga3 kernels (internal interface).
+#pragma once
+
+#include "common.h"
+
+namespace nsga3 {
+
+// Phase-boundary hook (records a timing event when profiling is on).
+struct Marker {
+    void (*fn)(void *) = nullptr;
+    void *arg = nullptr;
+    void operator()() const {
+        if (fn) fn(arg);
+    }
+};
+
+// ---- sort_scan.hip --------------------------------------------------------
+size_t radix_sort_temp_bytes(int64_t n);
+void radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *k_alt, uint32_t *v_alt, int64_t n,
+                      int nbits, uint32_t *temp, hipStream_t s, bool *in_alt);
+size_t compact_temp_bytes(int64_t n);
+// Writes at most `cap` indices; *total (device) receives the number of set flags.
+void compact_flags(const uint8_t *flag, int64_t n, int32_t *out, int64_t cap, uint32_t *temp,
+                   uint32_t *total, hipStream_t s);
+
+// ---- dominance.hip --------------------------------------------------------
+// Pointers into the workspace used by the sorting stage (a0-a3).
+struct SortViews {
+    const float *objs;
+    int64_t N;
+    int M;
+    int64_t K;
+    uint64_t *skey, *skey_alt;   // [N] key sums
+    uint32_t *sval, *sval_alt;   // [N] point index (permutation)
+    uint32_t *temp;              // radix-sort / scan scratch
+    uint32_t *recs;              // [N * rec_stride(M)] sorted records
+    int32_t *runstart;           // [N]
+    int32_t *dom_in_s, *dom_out_s, *rank_s;  // [N] in sorted order
+    uint32_t *fk[2], *uk[2];     // peeling lists (records)
+    int32_t *urun[2], *ucnt[2];  // peeling lists (run starts, remaining in-degree)
+    int32_t *fsize;              // [N] front sizes
+    uint32_t *blkcnt;            // [2 * max grid] per-block counts
+    int32_t *rank, *dom_in, *dom_out;  // outputs in original order (dom_* may be null)
+    DevScalars *sc;
+    Marker mark;
+};
+
+struct LaunchCfg {
+    int num_cus;
+    int peel_blocks_per_cu;
+};
+
+hipError_t run_sort_stage(const SortViews &v, const LaunchCfg &cfg, hipStream_t s);
+// Largest cooperative grid the peeling kernel may use for this M (0 on error).
+int peel_max_blocks_per_cu(int M);
+
+// ---- select.hip -----------------------------------------------------------
+struct SelectViews {
+    const float *objs;
+    int64_t N;
+    int M;
+    const float *refs;
+    int H;
+    int64_t K;
+    const int32_t *rank;         // [N] original order
+    int32_t *niche;              // [N]
+    float *dist;                 // [N] or null
+    double *dist64;              // [N]
+    double *rhat64;              // [H*M]
+    float *rhat32;               // [H*M]
+    double *p_asf;               // [nb * M]
+    int32_t *p_idx;              // [nb * M]
+    double *p_nad;               // [nb * M]
+    int32_t *rho, *bcount, *bstart, *bcursor;  // [H], [H], [H+1], [H]
+    double *bd;                  // [N] bucketed distances
+    int32_t *bi;                 // [N] bucketed indices
+    uint8_t *selflag;            // [N]
+    uint32_t *temp;
+    int32_t *selected;           // [K]
+    nsga3_info *info;            // caller's, may be null
+    DevScalars *sc;
+    int assoc_mode;
+    Marker mark;
+};
+
+int normalize_partial_blocks(int64_t N);
+hipError_t run_refs(const float *refs, int H, int M, double *rhat64, float *rhat32, DevScalars *sc,
+                    hipStream_t s);
+hipError_t run_select_stage(const SelectViews &v, hipStream_t s);
+hipError_t run_init(DevScalars *sc, int32_t *zero_i32[], const int64_t zero_n[], int nzero,
+                    hipStream_t s);
+
+}  // namespace nsga3

@@ -1,0 +1,568 @@
+// Normalisation, association, niche counting and niche-preserving selection
+// on gfx950 (stages after the nondominated sort).
+//
+//  a4/a5  Alg. S.5: ideal point z (minimum over all points, which equals the
+//         minimum over S = {rank <= l}: every minimiser of an objective is
+//         dominated only by other minimisers, so one of them is nondominated),
+//         extreme points by the achievement scalarising function with weights
+//         1 (own axis) and 1e-6 (other axes, applied as x 1e6), hyperplane
+//         intercepts from E b = 1 by Gaussian elimination with partial
+//         pivoting in float64, with the nadir point as fallback.
+//  a6     Eq. (10): perpendicular distance of f' = (f - z) / a to every
+//         reference line.  argmin_j d_ij = argmax_j f'.rhat_j (f', rhat >= 0),
+//         so candidates are screened by that dot product in float32 and the
+//         survivors are re-scored in float64 with the residual form
+//         ||f' - (f'.rhat) rhat||.
+//  a7     Eq. (11): niche counts rho over the admitted members (rank < l) and
+//         the per-reference member counts of the last front (Eq. (12)).
+//  a8     Alg. S.1 inner loop, evaluated in parallel: last-front member i of
+//         reference j gets the level rho_j + t_i, t_i its position among the
+//         members of j ordered by (distance, index); the loop picks exactly the
+//         R smallest (level, reference) pairs, found by a threshold search.
+//  a9     Eq. (13): ascending indices of the selected points.
+#include <float.h>
+
+#include "kernels.h"
+#include "prims.h"
+
+namespace nsga3 {
+
+constexpr int kNormThreads = 256;
+constexpr int kNormBlocksMax = 1024;
+
+// ---------------------------------------------------------------------------
+// init: clear per-call scalars and counters (fill kernels, no memset nodes)
+// ---------------------------------------------------------------------------
+__global__ void k_init_scalars(DevScalars *sc) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        sc->err = 0;
+        sc->last_front = 0;
+        sc->num_fronts = 0;
+        sc->last_front_size = 0;
+        sc->n_before = 0;
+        sc->num_from_last = 0;
+        sc->fallback = 0;
+        sc->near_ties = 0;
+        sc->nf = sc->nu = 0;
+        sc->bar_count = 0;
+        sc->bar_gen = 0;
+        sc->level_V = 0;
+        sc->ref_thr = 0;
+    }
+    if (t < 16) {
+        sc->min_key[t] = 0xffffffffu;
+        sc->a[t] = 1.0;
+        sc->z[t] = 0.0;
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+hipError_t run_init(DevScalars *sc, int32_t *zero_i32[], const int64_t zero_n[], int nzero,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, s, sc);
+    for (int q = 0; q < nzero; ++q) {
+        if (!zero_i32[q] || zero_n[q] <= 0) continue;
+        int64_t nb = (zero_n[q] + 255) / 256;
+        if (nb > 2048) nb = 2048;
+        hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)nb), dim3(256), 0, s, zero_i32[q], zero_n[q], 0);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// reference directions: validity and unit vectors (float64 and float32)
+// ---------------------------------------------------------------------------
+__global__ void k_refs(const float *__restrict__ refs, int H, int M, double *__restrict__ rhat64,
+                       float *__restrict__ rhat32, DevScalars *__restrict__ sc) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= H) return;
+    double nn = 0.0;
+    bool bad = false;
+    for (int k = 0; k < M; ++k) {
+        const float f = refs[(int64_t)j * M + k];
+        bad |= !__builtin_isfinite(f) || f < 0.0f;
+        const double v = (double)f;
+        nn = nn + v * v;
+    }
+    const double n = sqrt(nn);
+    bad |= !(n > 0.0) || !__builtin_isfinite(n);
+    if (bad) {
+        atomicOr(&sc->err, (uint32_t)kErrBadRef);
+        return;
+    }
+    for (int k = 0; k < M; ++k) {
+        const double r = (double)refs[(int64_t)j * M + k] / n;
+        rhat64[(int64_t)j * M + k] = r;
+        rhat32[(int64_t)j * M + k] = (float)r;
+    }
+}
+
+__device__ __forceinline__ double ideal(const DevScalars *sc, int k) {
+    return (double)key_to_float(sc->min_key[k]);
+}
+
+// ---------------------------------------------------------------------------
+// a4: extreme-point partials per block (ASF argmin per axis) and nadir partials
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kNormThreads) void k_extreme_partial(
+    const float *__restrict__ objs, int64_t N, int M, const int32_t *__restrict__ rank,
+    const DevScalars *__restrict__ sc, double *__restrict__ p_asf, int32_t *__restrict__ p_idx,
+    double *__restrict__ p_nad) {
+    __shared__ double s_asf[kNormThreads / kWave][16];
+    __shared__ int32_t s_idx[kNormThreads / kWave][16];
+    __shared__ double s_nad[kNormThreads / kWave][16];
+    if (sc->err) return;
+    const int32_t l = sc->last_front;
+    double z[16], best[16], nad[16];
+    int32_t bidx[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        z[k] = k < M ? ideal(sc, k) : 0.0;
+        best[k] = DBL_MAX;
+        bidx[k] = 0x7fffffff;
+        nad[k] = 0.0;
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        if (rank[i] > l) continue;
+        double g[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            g[k] = k < M ? (double)objs[i * M + k] - z[k] : 0.0;
+            if (k < M && g[k] > nad[k]) nad[k] = g[k];
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if (j < M) {
+                double asf = -DBL_MAX;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    if (k < M) {
+                        const double v = (k == j) ? g[k] : g[k] * 1e6;
+                        if (v > asf) asf = v;
+                    }
+                }
+                if (asf < best[j]) { best[j] = asf; bidx[j] = (int32_t)i; }
+            }
+        }
+    }
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j >= M) continue;
+        double b = best[j];
+        int32_t bi = bidx[j];
+        double nd = nad[j];
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(b, o, 64);
+            const int32_t oi = __shfl_xor(bi, o, 64);
+            if (ob < b || (ob == b && oi < bi)) { b = ob; bi = oi; }
+            const double on = __shfl_xor(nd, o, 64);
+            nd = on > nd ? on : nd;
+        }
+        if (lane_id() == 0) { s_asf[w][j] = b; s_idx[w][j] = bi; s_nad[w][j] = nd; }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < M) {
+        const int j = threadIdx.x;
+        double b = s_asf[0][j];
+        int32_t bi = s_idx[0][j];
+        double nd = s_nad[0][j];
+        for (int q = 1; q < kNormThreads / kWave; ++q) {
+            if (s_asf[q][j] < b || (s_asf[q][j] == b && s_idx[q][j] < bi)) { b = s_asf[q][j]; bi = s_idx[q][j]; }
+            nd = s_nad[q][j] > nd ? s_nad[q][j] : nd;
+        }
+        p_asf[blockIdx.x * M + j] = b;
+        p_idx[blockIdx.x * M + j] = bi;
+        p_nad[blockIdx.x * M + j] = nd;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a5: reduce the partials, build E, solve E b = 1, intercepts / fallback.
+// One wave.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_solve(const float *__restrict__ objs, int M, int nparts,
+                                              const double *__restrict__ p_asf,
+                                              const int32_t *__restrict__ p_idx,
+                                              const double *__restrict__ p_nad,
+                                              DevScalars *__restrict__ sc) {
+    __shared__ int32_t s_e[16];
+    __shared__ double s_nadir[16];
+    if (sc->err) return;
+    for (int j = 0; j < M; ++j) {
+        double b = DBL_MAX;
+        int32_t bi = 0x7fffffff;
+        double nd = 0.0;
+        for (int q = threadIdx.x; q < nparts; q += 64) {
+            const double a = p_asf[q * M + j];
+            const int32_t ai = p_idx[q * M + j];
+            if (a < b || (a == b && ai < bi)) { b = a; bi = ai; }
+            const double n = p_nad[q * M + j];
+            nd = n > nd ? n : nd;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(b, o, 64);
+            const int32_t oi = __shfl_xor(bi, o, 64);
+            if (ob < b || (ob == b && oi < bi)) { b = ob; bi = oi; }
+            const double on = __shfl_xor(nd, o, 64);
+            nd = on > nd ? on : nd;
+        }
+        if (threadIdx.x == 0) { s_e[j] = bi; s_nadir[j] = nd; }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double z[16];
+    for (int k = 0; k < M; ++k) { z[k] = ideal(sc, k); sc->z[k] = z[k]; }
+    double A[16 * 16], rhs[16], b[16], a[16];
+    double maxabs = 0.0;
+    for (int j = 0; j < M; ++j) {
+        for (int k = 0; k < M; ++k) {
+            const double e = (double)objs[(int64_t)s_e[j] * M + k] - z[k];
+            A[j * M + k] = e;
+            const double v = fabs(e);
+            if (v > maxabs) maxabs = v;
+        }
+        rhs[j] = 1.0;
+    }
+    bool ok = maxabs > 0.0;
+    for (int c = 0; c < M && ok; ++c) {
+        int p = c;
+        double pv = fabs(A[c * M + c]);
+        for (int r = c + 1; r < M; ++r) {
+            const double v = fabs(A[r * M + c]);
+            if (v > pv) { pv = v; p = r; }
+        }
+        if (!(pv > 1e-10 * maxabs)) { ok = false; break; }
+        if (p != c) {
+            for (int k = 0; k < M; ++k) {
+                const double t = A[c * M + k];
+                A[c * M + k] = A[p * M + k];
+                A[p * M + k] = t;
+            }
+            const double t = rhs[c]; rhs[c] = rhs[p]; rhs[p] = t;
+        }
+        for (int r = c + 1; r < M; ++r) {
+            const double f = A[r * M + c] / A[c * M + c];
+            for (int k = c + 1; k < M; ++k) A[r * M + k] = A[r * M + k] - f * A[c * M + k];
+            A[r * M + c] = 0.0;
+            rhs[r] = rhs[r] - f * rhs[c];
+        }
+    }
+    if (ok) {
+        for (int c = M - 1; c >= 0; --c) {
+            double s = rhs[c];
+            for (int k = c + 1; k < M; ++k) s = s - A[c * M + k] * b[k];
+            b[c] = s / A[c * M + c];
+        }
+        for (int k = 0; k < M && ok; ++k) {
+            if (!(__builtin_isfinite(b[k]) && b[k] > 0.0)) { ok = false; break; }
+            const double ak = 1.0 / b[k];
+            if (!__builtin_isfinite(ak)) { ok = false; break; }
+            a[k] = ak;
+        }
+    }
+    int fb = 0;
+    if (!ok) {
+        fb = 1;
+        for (int k = 0; k < M; ++k) a[k] = s_nadir[k];
+    }
+    for (int k = 0; k < M; ++k)
+        if (a[k] == 0.0) { a[k] = 1.0; fb = 2; }
+    for (int k = 0; k < M; ++k) sc->a[k] = a[k];
+    sc->fallback = fb;
+}
+
+// ---------------------------------------------------------------------------
+// a6/a7: association (float32 screening, float64 re-scoring) and counts
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kNormThreads) void k_associate(
+    const float *__restrict__ objs, int64_t N, int M, const int32_t *__restrict__ rank,
+    const double *__restrict__ rhat64, const float *__restrict__ rhat32, int H,
+    int32_t *__restrict__ niche, float *__restrict__ dist, double *__restrict__ dist64,
+    int32_t *__restrict__ rho, int32_t *__restrict__ bcount, uint8_t *__restrict__ selflag,
+    DevScalars *__restrict__ sc) {
+    if (sc->err) return;
+    const int32_t l = sc->last_front;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t r = rank[i];
+    if (r > l) {
+        niche[i] = -1;
+        if (dist) dist[i] = -1.0f;
+        dist64[i] = -1.0;
+        selflag[i] = 0;
+        return;
+    }
+    double fp[16];
+    float y[16];
+    double mx = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        fp[k] = 0.0;
+        if (k < M) {
+            fp[k] = ((double)objs[i * M + k] - sc->z[k]) / sc->a[k];
+            mx = fp[k] > mx ? fp[k] : mx;
+        }
+    }
+    float l1 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        y[k] = (k < M && mx > 0.0) ? (float)(fp[k] / mx) : 0.0f;
+        l1 += y[k];
+    }
+    // screening: s_j = y . rhat_j in float32 (scale of y does not move argmax)
+    float smax = -FLT_MAX;
+    for (int j = 0; j < H; ++j) {
+        const float *rr = rhat32 + (int64_t)j * M;
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (k < M) s = __fmaf_rn(y[k], rr[k], s);
+        smax = s > smax ? s : smax;
+    }
+    // |s32 - s| <= (M + 3) u ||y||_2 <= (M + 3) u ||y||_1 with u = 2^-24; keep a
+    // wide margin so every reference within float64 reach of the best survives
+    const float band = 4.0f * (float)(M + 4) * 5.9604645e-8f * l1 + 1e-30f;
+    const float thr = smax - band;
+    double d1 = DBL_MAX, d2 = DBL_MAX;
+    int32_t best = 0;
+    for (int j = 0; j < H; ++j) {
+        const float *rr = rhat32 + (int64_t)j * M;
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (k < M) s = __fmaf_rn(y[k], rr[k], s);
+        if (s < thr) continue;
+        const double *rd = rhat64 + (int64_t)j * M;
+        double s64 = 0.0;
+        for (int k = 0; k < M; ++k) s64 = s64 + fp[k] * rd[k];
+        double q = 0.0;
+        for (int k = 0; k < M; ++k) {
+            const double e = fp[k] - s64 * rd[k];
+            q = q + e * e;
+        }
+        const double d = sqrt(q);
+        if (d < d1) { d2 = d1; d1 = d; best = j; }
+        else if (d < d2) { d2 = d; }
+    }
+    niche[i] = best;
+    if (dist) dist[i] = (float)d1;
+    dist64[i] = d1;
+    if (d2 != DBL_MAX && (d2 - d1) < 1e-6 * fmax(d2, 1e-300)) atomicAdd(&sc->near_ties, 1);
+    if (r < l) {
+        atomicAdd(&rho[best], 1);
+        selflag[i] = 1;
+    } else {
+        atomicAdd(&bcount[best], 1);
+        selflag[i] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a8 plan: bucket offsets of the last front by reference, and the selection
+// threshold.  For threshold V, C(V) = sum_j clamp(V - rho_j, 0, b_j) members
+// have level < V.  V* = max{V : C(V) <= R}; the remaining R - C(V*) picks are
+// the level-V* members of the lowest-indexed references.  One block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_niche_plan(int H, const int32_t *__restrict__ rho,
+                                                     const int32_t *__restrict__ bcount,
+                                                     int32_t *__restrict__ bstart,
+                                                     int32_t *__restrict__ bcursor,
+                                                     DevScalars *__restrict__ sc) {
+    __shared__ uint32_t lds[17];
+    __shared__ int64_t red[16];
+    __shared__ int64_t s_vmax;
+    if (sc->err) return;
+    const int64_t R = sc->num_from_last;
+    // bucket starts (exclusive scan of bcount), chunked by blockDim
+    uint32_t run = 0;
+    int64_t vmax = 0;
+    for (int base = 0; base < H; base += blockDim.x) {
+        const int j = base + threadIdx.x;
+        const uint32_t v = j < H ? (uint32_t)bcount[j] : 0u;
+        if (j < H) {
+            const int64_t top = (int64_t)rho[j] + bcount[j];
+            vmax = top > vmax ? top : vmax;
+        }
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(v, lds, &tot);
+        if (j < H) { bstart[j] = (int32_t)(run + ex); bcursor[j] = (int32_t)(run + ex); }
+        run += tot;
+    }
+    if (threadIdx.x == 0) bstart[H] = (int32_t)run;
+    vmax = wave_max(vmax);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = vmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t m = 0;
+        for (unsigned q = 0; q < blockDim.x / kWave; ++q) m = red[q] > m ? red[q] : m;
+        s_vmax = m;
+    }
+    __syncthreads();
+    // binary search for V* in [0, vmax]: C is non-decreasing, C(0) = 0 <= R
+    int64_t lo = 0, hi = s_vmax;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        int64_t c = 0;
+        for (int j = threadIdx.x; j < H; j += blockDim.x) {
+            int64_t t = mid - rho[j];
+            t = t < 0 ? 0 : t;
+            c += t < bcount[j] ? t : bcount[j];
+        }
+        c = wave_sum(c);
+        __syncthreads();
+        if (lane_id() == 0) red[threadIdx.x / kWave] = c;
+        __syncthreads();
+        int64_t tot = 0;
+        for (unsigned q = 0; q < blockDim.x / kWave; ++q) tot += red[q];
+        if (tot <= R) lo = mid; else hi = mid - 1;
+    }
+    const int64_t V = lo;
+    int64_t cV = 0;
+    for (int j = threadIdx.x; j < H; j += blockDim.x) {
+        int64_t t = V - rho[j];
+        t = t < 0 ? 0 : t;
+        cV += t < bcount[j] ? t : bcount[j];
+    }
+    cV = wave_sum(cV);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x / kWave] = cV;
+    __syncthreads();
+    int64_t CV = 0;
+    for (unsigned q = 0; q < blockDim.x / kWave; ++q) CV += red[q];
+    const int64_t rem = R - CV;  // picks at level V, lowest references first
+    // reference threshold: the rem-th reference (ascending) with a member at level V
+    int32_t thr = 0;
+    uint32_t seen = 0;
+    __shared__ int32_t s_thr;
+    if (threadIdx.x == 0) s_thr = (rem <= 0) ? 0 : H;
+    __syncthreads();
+    if (rem > 0) {
+        for (int base = 0; base < H; base += blockDim.x) {
+            const int j = base + threadIdx.x;
+            const uint32_t has = (j < H && rho[j] <= V && V < (int64_t)rho[j] + bcount[j]) ? 1u : 0u;
+            uint32_t tot;
+            const uint32_t ex = block_exclusive_scan(has, lds, &tot);
+            if (has && (int64_t)(seen + ex) == rem - 1) s_thr = j + 1;
+            seen += tot;
+            __syncthreads();
+            if ((int64_t)seen >= rem) break;
+        }
+    }
+    __syncthreads();
+    thr = s_thr;
+    if (threadIdx.x == 0) {
+        sc->level_V = (int32_t)V;
+        sc->ref_thr = thr;
+    }
+}
+
+// last-front members -> reference buckets (order inside a bucket is arbitrary)
+__global__ __launch_bounds__(256) void k_bucket_scatter(int64_t N, const int32_t *__restrict__ rank,
+                                                        const int32_t *__restrict__ niche,
+                                                        const double *__restrict__ dist64,
+                                                        int32_t *__restrict__ bcursor,
+                                                        double *__restrict__ bd,
+                                                        int32_t *__restrict__ bi,
+                                                        const DevScalars *__restrict__ sc) {
+    if (sc->err) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N || rank[i] != sc->last_front) return;
+    const int32_t slot = atomicAdd(&bcursor[niche[i]], 1);
+    bd[slot] = dist64[i];
+    bi[slot] = (int32_t)i;
+}
+
+// t_i = #members of the same reference with smaller (distance, index); pick
+// when (rho + t, reference) is below the threshold.
+__global__ __launch_bounds__(256) void k_bucket_rank(int64_t nl, const int32_t *__restrict__ niche,
+                                                     const int32_t *__restrict__ rho,
+                                                     const int32_t *__restrict__ bstart,
+                                                     const double *__restrict__ bd,
+                                                     const int32_t *__restrict__ bi,
+                                                     uint8_t *__restrict__ selflag,
+                                                     const DevScalars *__restrict__ sc) {
+    if (sc->err) return;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n_l = sc->last_front_size;
+    if (s >= n_l || s >= nl) return;
+    const double d = bd[s];
+    const int32_t i = bi[s];
+    const int32_t j = niche[i];
+    const int32_t b0 = bstart[j], b1 = bstart[j + 1];
+    int32_t t = 0;
+    for (int32_t m = b0; m < b1; ++m) {
+        const double dm = bd[m];
+        const int32_t im = bi[m];
+        t += (dm < d || (dm == d && im < i)) ? 1 : 0;
+    }
+    const int64_t lev = (int64_t)rho[j] + t;
+    const int64_t V = sc->level_V;
+    if (lev < V || (lev == V && j < sc->ref_thr)) selflag[i] = 1;
+}
+
+__global__ void k_finalize(nsga3_info *info, int64_t K, const DevScalars *__restrict__ sc) {
+    if (threadIdx.x != 0) return;
+    uint32_t e = sc->err;
+    if (e == 0 && (int64_t)sc->n_selected != K) e |= kErrInternal;
+    nsga3_info v;
+    v.status = e == 0 ? NSGA3_OK
+               : (e & (kErrNonfiniteObj | kErrBadRef)) ? NSGA3_E_NONFINITE
+                                                       : NSGA3_E_HIP;
+    v.last_front = sc->last_front;
+    v.num_fronts = sc->num_fronts;
+    v.last_front_size = sc->last_front_size;
+    v.num_from_last = (int32_t)sc->num_from_last;
+    v.intercept_fallback = sc->fallback;
+    v.near_ties = sc->near_ties;
+    v.reserved = (int32_t)e;
+    *info = v;
+}
+
+int normalize_partial_blocks(int64_t N) {
+    int64_t nb = (N + kNormThreads - 1) / kNormThreads;
+    if (nb > kNormBlocksMax) nb = kNormBlocksMax;
+    if (nb < 1) nb = 1;
+    return (int)nb;
+}
+
+hipError_t run_select_stage(const SelectViews &v, hipStream_t s) {
+    const int64_t N = v.N;
+    const int M = v.M;
+    const int nparts = normalize_partial_blocks(N);
+    v.mark();
+    hipLaunchKernelGGL(k_extreme_partial, dim3(nparts), dim3(kNormThreads), 0, s, v.objs, N, M,
+                       v.rank, v.sc, v.p_asf, v.p_idx, v.p_nad);
+    hipLaunchKernelGGL(k_solve, dim3(1), dim3(64), 0, s, v.objs, M, nparts, v.p_asf, v.p_idx,
+                       v.p_nad, v.sc);
+    const unsigned nbN = (unsigned)((N + 255) / 256);
+    v.mark();
+    hipLaunchKernelGGL(k_associate, dim3(nbN), dim3(kNormThreads), 0, s, v.objs, N, M, v.rank,
+                       v.rhat64, v.rhat32, v.H, v.niche, v.dist, v.dist64, v.rho, v.bcount,
+                       v.selflag, v.sc);
+    v.mark();
+    hipLaunchKernelGGL(k_niche_plan, dim3(1), dim3(1024), 0, s, v.H, v.rho, v.bcount, v.bstart,
+                       v.bcursor, v.sc);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(nbN), dim3(256), 0, s, N, v.rank, v.niche, v.dist64,
+                       v.bcursor, v.bd, v.bi, v.sc);
+    hipLaunchKernelGGL(k_bucket_rank, dim3(nbN), dim3(256), 0, s, N, v.niche, v.rho, v.bstart, v.bd,
+                       v.bi, v.selflag, v.sc);
+    compact_flags(v.selflag, N, v.selected, v.K, v.temp, &v.sc->n_selected, s);
+    if (v.info) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, v.info, v.K, v.sc);
+    v.mark();
+    return hipGetLastError();
+}
+
+hipError_t run_refs(const float *refs, int H, int M, double *rhat64, float *rhat32, DevScalars *sc,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_refs, dim3((H + 255) / 256), dim3(256), 0, s, refs, H, M, rhat64, rhat32, sc);
+    return hipGetLastError();
+}
+
+}  // namespace nsga3

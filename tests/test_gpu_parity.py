@@ -1,0 +1,229 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Ranks, fronts, dominance counts, l, |F_l|, R and the selected indices must be
+bit-exact.  Reference-line indices must match except where the oracle's two
+closest lines are within 1e-6 relative distance; distances must agree within
+1e-5 * max(1, ||f'||) of the float64 oracle."""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_helpers import compare_full, dist_close, gpu_select
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_worked.json")
+
+
+def _zero(rep):
+    bad = {k: v for k, v in rep.items() if k != "near_ties" and v}
+    assert not bad, f"mismatches: {rep}"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2503_20286_amd as nsga3
+    nsga3.load()
+    oracle.lib()
+
+
+def test_hand_worked_cases():
+    with open(GOLDEN) as fh:
+        cases = json.load(fh)["cases"]
+    for c in cases:
+        F = np.asarray(c["objs"], np.float32)
+        R = np.asarray(c["refs"], np.float32)
+        g = gpu_select(F, R, c["K"])
+        assert g["selected"].tolist() == c["selected"], c["name"]
+        assert g["rank"].tolist() == c["rank"]
+        assert g["dom_in"].tolist() == c["dom_in"]
+        assert g["dom_out"].tolist() == c["dom_out"]
+        assert g["niche"].tolist() == c["niche"]
+        info = g["info"]
+        assert (info.status, info.last_front, info.last_front_size) == (0, c["last_front"], c["last_front_size"])
+        for i, (num, den) in enumerate(zip(c["dist_num"], c["dist_den"])):
+            if num is None:
+                assert g["dist"][i] == -1.0
+            else:
+                assert abs(g["dist"][i] - num / den) <= 1e-6
+
+
+@pytest.mark.parametrize("name,N", [("small", None), ("ties", 3000), ("large", 5000), ("many", 4000),
+                                    ("ties", None)])
+def test_workload_full_parity(name, N):
+    w = workloads.make(name, N=N)
+    print(f"case {name} N={w.N} M={w.M} H={w.H} K={w.K}", flush=True)
+    g = gpu_select(w.objs, w.refs, w.K)
+    _zero(compare_full(w.objs, w.refs, w.K, g))
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 63, 64, 65, 1023, 1024, 1025, 4097])
+def test_sizes_and_ragged_tails(N):
+    w = workloads.make("large", N=N, seed=77)
+    for K in sorted({1, max(1, N // 2), N}):
+        print(f"ragged N={N} K={K}", flush=True)
+        g = gpu_select(w.objs, w.refs, K)
+        _zero(compare_full(w.objs, w.refs, K, g))
+
+
+def test_duplicates_and_equal_sums():
+    rng = np.random.default_rng(5)
+    base = rng.integers(0, 6, size=(700, 3)).astype(np.float32)
+    F = np.concatenate([base, base[:300], base[::-1][:200]])       # many identical rows
+    R = workloads.das_dennis(3, 5).astype(np.float32)
+    for K in (1, 37, 600, F.shape[0]):
+        g = gpu_select(F, R, K)
+        _zero(compare_full(F, R, K, g))
+
+
+def test_long_chain_many_fronts():
+    # points on a line: each dominates every later one -> N fronts
+    t = np.arange(600, dtype=np.float32)
+    F = np.stack([t, 2 * t + 1, t + 3], axis=1)[np.random.default_rng(1).permutation(600)]
+    R = workloads.das_dennis(3, 4).astype(np.float32)
+    g = gpu_select(F, R, 300)
+    assert g["info"].num_fronts == 600
+    _zero(compare_full(F, R, 300, g))
+
+
+@pytest.mark.parametrize("M", [2, 4, 7, 8, 12, 16])
+def test_objective_counts(M):
+    rng = np.random.default_rng(M)
+    F = workloads.sphere_shell(rng, 1500, M, lambda g, n: g.uniform(0, 0.4, n), 0.2).astype(np.float32)
+    p = {2: 20, 4: 5, 7: 2, 8: 2, 12: 1, 16: 1}[M]
+    R = workloads.das_dennis(M, p).astype(np.float32)
+    g = gpu_select(F, R, 700)
+    _zero(compare_full(F, R, 700, g))
+
+
+def test_negative_and_signed_zero_objectives():
+    w = workloads.make("ties", N=2000, seed=9)
+    F = w.objs.copy() - np.float32(0.75)
+    F[::5, 1] = -0.0
+    F[1::5, 1] = 0.0
+    g = gpu_select(F, w.refs, 1000)
+    _zero(compare_full(F, w.refs, 1000, g))
+
+
+def test_nonfinite_and_bad_reference_report_status():
+    w = workloads.make("small")
+    bad = w.objs.copy()
+    bad[17, 2] = np.nan
+    assert gpu_select(bad, w.refs, w.K)["info"].status == -2
+    bad = w.objs.copy()
+    bad[3, 0] = np.inf
+    assert gpu_select(bad, w.refs, w.K)["info"].status == -2
+    R = w.refs.copy()
+    R[4, 1] = -0.5
+    assert gpu_select(w.objs, R, w.K)["info"].status == -2
+    R = w.refs.copy()
+    R[0] = 0.0
+    assert gpu_select(w.objs, R, w.K)["info"].status == -2
+    # the context keeps working after a device-side error
+    g = gpu_select(w.objs, w.refs, w.K)
+    _zero(compare_full(w.objs, w.refs, w.K, g))
+
+
+def test_host_checked_errors():
+    import torch
+    import paper_2503_20286_amd as nsga3
+    w = workloads.make("small")
+    o = torch.from_numpy(w.objs).cuda()
+    r = torch.from_numpy(w.refs).cuda()
+    for K in (0, w.N + 1):
+        with pytest.raises(nsga3.NativeError) as e:
+            nsga3.select(o, r, K)
+        assert e.value.code == -1
+    with pytest.raises(nsga3.NativeError):
+        nsga3.select(o[:, :1].contiguous(), r[:, :1].contiguous(), 10)   # M = 1
+    big = torch.zeros((4, 17), dtype=torch.float32, device="cuda")
+    with pytest.raises(nsga3.NativeError):
+        nsga3.select(big, torch.ones((3, 17), dtype=torch.float32, device="cuda"), 2)
+
+
+def test_repeat_calls_bit_identical_and_smaller_after_larger():
+    w = workloads.make("ties", N=6000)
+    a = gpu_select(w.objs, w.refs, w.K)
+    b = gpu_select(w.objs, w.refs, w.K)
+    for k in ("selected", "rank", "niche", "dist", "dom_in", "dom_out"):
+        assert np.array_equal(a[k], b[k]), k
+    s = workloads.make("small")
+    g = gpu_select(s.objs, s.refs, s.K)
+    _zero(compare_full(s.objs, s.refs, s.K, g))
+
+
+def test_power_of_two_scaling_gives_identical_outputs():
+    w = workloads.make("large", N=4000)
+    a = gpu_select(w.objs, w.refs, w.K)
+    b = gpu_select(np.ldexp(w.objs, 3).astype(np.float32), w.refs, w.K)
+    for k in ("selected", "rank", "niche", "dist", "dom_in", "dom_out"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads (the shapes the benchmark times), checked on samples and
+# by properties that hold at any size.
+# ---------------------------------------------------------------------------
+def _check_large_scale(w, n_samples=48, seed=0):
+    g = gpu_select(w.objs, w.refs, w.K)
+    F = w.objs
+    N = w.N
+    info = g["info"]
+    assert info.status == 0
+    rank = g["rank"]
+    # fronts: sizes and last front from the GPU ranks follow the closed form
+    sizes = np.bincount(rank)
+    assert info.num_fronts == sizes.size and np.all(sizes > 0)
+    l, nb, nl = oracle.last_front(rank, w.K)
+    assert (info.last_front, info.last_front_size, info.num_from_last) == (l, nl, w.K - nb)
+    # sampled points: dominance counts by the oracle one at a time, and the
+    # rank property "no dominator in the same or a later front, one dominator
+    # exactly one front earlier" (which characterises the ranks)
+    rng = np.random.default_rng(seed)
+    sample = rng.choice(N, size=min(n_samples, N), replace=False)
+    F64 = F.astype(np.float64)
+    for j in sample:
+        din, dout = oracle.dominance_one(F, int(j))
+        assert (g["dom_in"][j], g["dom_out"][j]) == (din, dout), f"counts of {j}"
+        le = np.all(F64 <= F64[j], axis=1) & np.any(F64 < F64[j], axis=1)
+        dr = rank[le]
+        if rank[j] == 0:
+            assert dr.size == 0
+        else:
+            assert dr.max() == rank[j] - 1
+    assert int(g["dom_in"].sum()) == int(g["dom_out"].sum())
+    # normalisation, association and niching re-run by the oracle on the GPU ranks
+    nz = oracle.normalize(F, rank, l)
+    assert info.intercept_fallback == nz.fallback
+    niche, dist, gap = oracle.associate(F, rank, l, nz.z, nz.a, w.refs)
+    S = rank <= l
+    tie = S & (gap < 1e-6)
+    assert int(np.sum((g["niche"] != niche) & ~tie)) == 0
+    fpn = np.linalg.norm((F64 - nz.z) / nz.a, axis=1)
+    assert np.all(np.where(S, dist_close(g["dist"], dist, fpn), g["dist"] == -1.0) | tie)
+    rho = oracle.niche_count(rank, g["niche"], l, w.H)
+    chosen = oracle.niching(rank, g["niche"], dist, l, w.H, w.K - nb, rho)
+    want = np.nonzero((rank < l) | chosen)[0]
+    assert np.array_equal(g["selected"], want)
+    return g
+
+
+def test_large_full_size_sampled():
+    w = workloads.make("large")
+    print(f"large N={w.N}", flush=True)
+    _check_large_scale(w)
+
+
+def test_many_objectives_full_size_sampled():
+    w = workloads.make("many")
+    print(f"many N={w.N}", flush=True)
+    _check_large_scale(w, n_samples=24)
