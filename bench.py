@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=60000)
     ap.add_argument("--check", action="store_true", help="verify one timed result (sampled)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (three times), to scale "
+                         "the FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
 
 
@@ -81,6 +84,15 @@ def main():
     if not torch.cuda.is_available():
         print("no HIP device visible", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4}), flush=True)
+        return
     nsga3.load()
     w = workloads.make(args.workload)
     dev = torch.device("cuda:0")

@@ -32,7 +32,7 @@ struct Layout {
     size_t skey, skey_alt, sval, sval_alt, temp, recs, runstart, dom_in_s, dom_out_s, rank_s;
     size_t fk0, fk1, uk0, uk1, urun0, urun1, ucnt0, ucnt1, fsize, blkcnt;
     size_t rank, niche, dist64, rhat64, rhat32, p_asf, p_idx, p_nad;
-    size_t rho, bcount, bstart, bcursor, bd, bi, selflag, sc;
+    size_t rho, bcount, bstart, bcursor, bd, bi, selflag, sc, bar;
     size_t total;
 };
 
@@ -87,6 +87,7 @@ Layout layout_for(int64_t N, int M, int H, int max_grid) {
     L.bi = bump(c, 4 * n);
     L.selflag = bump(c, n);
     L.sc = bump(c, sizeof(DevScalars));
+    L.bar = bump(c, sizeof(GridBar));
     L.total = c;
     return L;
 }
@@ -200,9 +201,16 @@ nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt)
     c->num_cus = prop.multiProcessorCount;
     DeviceGuard g(device);
     for (int m = 0; m <= 16; ++m) c->peel_bpc[m] = 0;
+    // NSGA3_PEEL_BLOCKS_PER_CU overrides the co-resident blocks per CU of the
+    // peeling kernel (tuning); it is clamped to what the device can co-schedule.
+    int want = kMaxPeelBlocksPerCu;
+    if (const char *e = getenv("NSGA3_PEEL_BLOCKS_PER_CU")) {
+        const int v = atoi(e);
+        if (v >= 1 && v <= 16) want = v;
+    }
     for (int m = 2; m <= 16; ++m) {
         int nb = peel_max_blocks_per_cu(m);
-        c->peel_bpc[m] = nb < kMaxPeelBlocksPerCu ? nb : kMaxPeelBlocksPerCu;
+        c->peel_bpc[m] = nb < want ? nb : want;
         if (c->peel_bpc[m] < 1 || c->num_cus * c->peel_bpc[m] > kGridCap) {
             delete c;
             return NSGA3_E_UNSUPPORTED;
@@ -281,9 +289,9 @@ nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t 
     mk.arg = &marks;
     marks.mark();
     int32_t *zero_p[] = {WS(int32_t, dom_in_s), WS(int32_t, dom_out_s), WS(int32_t, rho),
-                         WS(int32_t, bcount)};
-    const int64_t zero_n[] = {N, N, H, H};
-    hipError_t e = run_init(sc, zero_p, zero_n, 4, stream);
+                         WS(int32_t, bcount), WS(int32_t, bar)};
+    const int64_t zero_n[] = {N, N, H, H, (int64_t)(sizeof(GridBar) / sizeof(int32_t))};
+    hipError_t e = run_init(sc, zero_p, zero_n, 5, stream);
     if (e == hipSuccess) e = run_refs(refs, H, M, WS(double, rhat64), WS(float, rhat32), sc, stream);
 
     SortViews sv;
@@ -315,6 +323,7 @@ nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t 
     sv.dom_in = dom_in;
     sv.dom_out = dom_out;
     sv.sc = sc;
+    sv.bar = WS(GridBar, bar);
     sv.mark = mk;
     LaunchCfg cfg;
     cfg.num_cus = ctx->num_cus;

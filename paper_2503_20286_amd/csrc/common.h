@@ -50,13 +50,28 @@ struct DevScalars {
     int32_t fallback;          // intercept fallback code
     int32_t near_ties;
     int32_t nf, nu;            // peeling list sizes (current level)
-    uint32_t bar_count;        // grid barrier
+    uint32_t bar_count;        // grid barrier (flat form)
     uint32_t bar_gen;
     int32_t level_V;           // niching threshold level
     int32_t ref_thr;           // niching threshold reference
     uint32_t n_selected;       // number of selection flags set (must equal K)
     double a[16];              // intercepts
     double z[16];              // ideal point (float64 of the float32 minimum)
+};
+
+// Two-level grid barrier state: blocks arrive on one of kBarSub counters
+// (each on its own 128-byte line), the last arriver of a group arrives at the
+// root, and the last group releases every group's flag.  Keeping arrivals and
+// polling spread over separate lines avoids one hot address.
+constexpr int kBarSub = 16;
+struct alignas(128) BarLine {
+    uint32_t v;
+    uint32_t pad[31];
+};
+struct GridBar {
+    BarLine count[kBarSub];
+    BarLine flag[kBarSub];
+    BarLine root;
 };
 
 struct Ws;  // workspace views, defined in the runtime

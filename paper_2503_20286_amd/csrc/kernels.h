@@ -42,6 +42,7 @@ struct SortViews {
     uint32_t *blkcnt;            // [2 * max grid] per-block counts
     int32_t *rank, *dom_in, *dom_out;  // outputs in original order (dom_* may be null)
     DevScalars *sc;
+    GridBar *bar;                // grid-barrier state (zeroed per call)
     Marker mark;
 };
 

@@ -74,49 +74,98 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *l
 }
 
 // ---------------------------------------------------------------------------
-// Grid barrier for cooperative (co-resident) launches.  Every block of the grid
-// must call it the same number of times.  A bounded spin turns a lost block
-// into an error flag instead of a hang; blocks then leave their loops.
+// Grid barriers for cooperative (co-resident) launches.  Every block of the
+// grid must call them the same number of times.  Memory ordering: each block's
+// thread 0 issues one release fence before arriving (its block's writes become
+// visible device-wide) and one acquire fence after leaving; arrival counters
+// and release flags use relaxed device-scope atomics, and polling uses relaxed
+// loads so that it does not invalidate caches on every probe.  A bounded spin
+// turns a lost block into an error flag instead of a hang; blocks then leave
+// their loops.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ bool barrier_spin(const uint32_t *flag, uint32_t g, uint32_t *err) {
+    uint64_t spins = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(2);
+        ++spins;
+        if ((spins & 1023u) == 0 &&
+            (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrBarrierTimeout))
+            return false;
+        if (spins > (1ull << 26)) {  // far beyond any legitimate wait
+            __hip_atomic_fetch_or(err, (uint32_t)kErrBarrierTimeout, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+    return true;
+}
+
+// Flat form: one arrival counter and one generation word.
 __device__ __forceinline__ bool grid_barrier(uint32_t *count, uint32_t *gen, uint32_t *err,
                                              uint32_t nblocks) {
     __syncthreads();
     __shared__ uint32_t s_ok;
     if (threadIdx.x == 0) {
-        uint32_t ok = 1;
-        const uint32_t g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
+        bool ok = true;
+        const uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // publish this block's writes
         const uint32_t arrived =
-            __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (arrived == nblocks - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            uint64_t spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(2);
-                ++spins;
-                if ((spins & 1023u) == 0 &&
-                    (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-                     kErrBarrierTimeout)) {
-                    ok = 0;
-                    break;
-                }
-                if (spins > (1ull << 26)) {  // far beyond any legitimate wait
-                    __hip_atomic_fetch_or(err, (uint32_t)kErrBarrierTimeout, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-            }
+            ok = barrier_spin(gen, g, err);
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see every block's writes
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrBarrierTimeout)
-            ok = 0;
-        s_ok = ok;
+            ok = false;
+        s_ok = ok ? 1u : 0u;
     }
     __syncthreads();
     return s_ok != 0;
+}
+
+// Two-level form (see GridBar): arrivals spread over kBarSub counters.
+__device__ __forceinline__ bool grid_barrier2(GridBar *bar, uint32_t *err) {
+    __syncthreads();
+    __shared__ uint32_t s_ok2;
+    if (threadIdx.x == 0) {
+        bool ok = true;
+        const uint32_t G = gridDim.x;
+        const uint32_t nsub = G < (uint32_t)kBarSub ? G : (uint32_t)kBarSub;
+        const uint32_t sub = blockIdx.x % nsub;
+        const uint32_t members = G / nsub + (sub < G % nsub ? 1u : 0u);
+        uint32_t *flag = &bar->flag[sub].v;
+        const uint32_t g = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        bool released = false;
+        const uint32_t a = __hip_atomic_fetch_add(&bar->count[sub].v, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        if (a == members - 1) {
+            __hip_atomic_store(&bar->count[sub].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            const uint32_t r = __hip_atomic_fetch_add(&bar->root.v, 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            if (r == nsub - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __hip_atomic_store(&bar->root.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                for (uint32_t q = 0; q < nsub; ++q)
+                    __hip_atomic_store(&bar->flag[q].v, g + 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                released = true;
+            }
+        }
+        if (!released) ok = barrier_spin(flag, g, err);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrBarrierTimeout)
+            ok = false;
+        s_ok2 = ok ? 1u : 0u;
+    }
+    __syncthreads();
+    return s_ok2 != 0;
 }
 
 }  // namespace nsga3
