@@ -19,6 +19,8 @@ struct nsga3_ctx {
     void *ws;
     size_t ws_bytes;
     bool profiling;
+    int phase_a_bpc;
+    volatile int32_t *last_fronts;  // pinned: front count of the latest call
     std::vector<hipEvent_t> ev_pool;   // NSGA3_NUM_PHASES + 1 events per recorded call
     size_t ev_used;
 };
@@ -26,11 +28,13 @@ struct nsga3_ctx {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxPeelBlocksPerCu = 2;
+constexpr int kMaxPeelBlocksPerCu = 4;
+constexpr int kDefaultHostLevels = 24;
 
 struct Layout {
     size_t skey, skey_alt, sval, sval_alt, temp, recs, runstart, dom_in_s, dom_out_s, rank_s;
-    size_t fk0, fk1, uk0, uk1, urun0, urun1, ucnt0, ucnt1, fsize, blkcnt;
+    size_t fk0, fk1, uk0, uk1, urun0, urun1, ucnt0, ucnt1, fsize, usize, work, lbstate, blkcnt;
+    size_t lb_stride;
     size_t rank, niche, dist64, rhat64, rhat32, p_asf, p_idx, p_nad;
     size_t rho, bcount, bstart, bcursor, bd, bi, selflag, sc, bar;
     size_t total;
@@ -70,6 +74,10 @@ Layout layout_for(int64_t N, int M, int H, int max_grid) {
     L.ucnt0 = bump(c, 4 * n);
     L.ucnt1 = bump(c, 4 * n);
     L.fsize = bump(c, 4 * n);
+    L.usize = bump(c, 4 * n);
+    L.work = bump(c, 4 * (size_t)kMaxHostLevels);
+    L.lb_stride = split_state_entries(N);
+    L.lbstate = bump(c, 8 * 2 * L.lb_stride);
     L.blkcnt = bump(c, 8 * (size_t)max_grid);
     L.rank = bump(c, 4 * n);
     L.niche = bump(c, 4 * n);
@@ -220,6 +228,21 @@ nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt)
     c->ws_bytes = 0;
     c->profiling = false;
     c->ev_used = 0;
+    c->phase_a_bpc = 8;
+    if (const char *e = getenv("NSGA3_PHASE_A_BLOCKS_PER_CU")) {
+        const int v = atoi(e);
+        if (v >= 1 && v <= 32) c->phase_a_bpc = v;
+    }
+    c->last_fronts = nullptr;
+    {
+        void *h = nullptr;
+        if (hipHostMalloc(&h, 64, hipHostMallocDefault) == hipSuccess) {
+            c->last_fronts = (volatile int32_t *)h;
+            *c->last_fronts = 0;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
     *out = c;
     return NSGA3_OK;
 }
@@ -229,6 +252,7 @@ void nsga3_destroy(nsga3_ctx *ctx) {
     {
         DeviceGuard g(ctx->device);
         if (ctx->ws) (void)hipFree(ctx->ws);
+        if (ctx->last_fronts) (void)hipHostFree((void *)ctx->last_fronts);
         for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     }
     delete ctx;
@@ -289,9 +313,11 @@ nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t 
     mk.arg = &marks;
     marks.mark();
     int32_t *zero_p[] = {WS(int32_t, dom_in_s), WS(int32_t, dom_out_s), WS(int32_t, rho),
-                         WS(int32_t, bcount), WS(int32_t, bar)};
-    const int64_t zero_n[] = {N, N, H, H, (int64_t)(sizeof(GridBar) / sizeof(int32_t))};
-    hipError_t e = run_init(sc, zero_p, zero_n, 5, stream);
+                         WS(int32_t, bcount), WS(int32_t, bar), WS(int32_t, work),
+                         WS(int32_t, lbstate)};
+    const int64_t zero_n[] = {N, N, H, H, (int64_t)(sizeof(GridBar) / sizeof(int32_t)),
+                              kMaxHostLevels, (int64_t)(2 * L.lb_stride)};
+    hipError_t e = run_init(sc, zero_p, zero_n, 7, stream);
     if (e == hipSuccess) e = run_refs(refs, H, M, WS(double, rhat64), WS(float, rhat32), sc, stream);
 
     SortViews sv;
@@ -318,6 +344,10 @@ nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t 
     sv.ucnt[0] = WS(int32_t, ucnt0);
     sv.ucnt[1] = WS(int32_t, ucnt1);
     sv.fsize = WS(int32_t, fsize);
+    sv.usize = WS(int32_t, usize);
+    sv.work = WS(uint32_t, work);
+    sv.lbstate = WS(uint64_t, lbstate);
+    sv.lb_stride = L.lb_stride;
     sv.blkcnt = WS(uint32_t, blkcnt);
     sv.rank = rank_o;
     sv.dom_in = dom_in;
@@ -328,7 +358,21 @@ nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t 
     LaunchCfg cfg;
     cfg.num_cus = ctx->num_cus;
     cfg.peel_blocks_per_cu = ctx->peel_bpc[M];
+    cfg.phase_a_blocks_per_cu = ctx->phase_a_bpc;
+    {
+        // enqueue one more level than the previous call needed (its front
+        // count arrives asynchronously in pinned memory; a stale value only
+        // shifts work between the enqueued levels and the cooperative tail)
+        const int prev = ctx->last_fronts ? *ctx->last_fronts : 0;
+        int lv = prev > 0 ? prev + 1 : kDefaultHostLevels;
+        if (lv > kMaxHostLevels) lv = kMaxHostLevels;
+        if (lv < 1) lv = 1;
+        cfg.host_levels = lv;
+    }
     if (e == hipSuccess) e = run_sort_stage(sv, cfg, stream);
+    if (e == hipSuccess && ctx->last_fronts)
+        e = hipMemcpyAsync((void *)ctx->last_fronts, &sc->num_fronts, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, stream);
 
     SelectViews xv;
     xv.objs = objs;

@@ -38,7 +38,11 @@ struct SortViews {
     int32_t *dom_in_s, *dom_out_s, *rank_s;  // [N] in sorted order
     uint32_t *fk[2], *uk[2];     // peeling lists (records)
     int32_t *urun[2], *ucnt[2];  // peeling lists (run starts, remaining in-degree)
-    int32_t *fsize;              // [N] front sizes
+    int32_t *fsize;              // [N] front sizes per level
+    int32_t *usize;              // [N] points still unranked after each level
+    uint32_t *work;              // [kMaxHostLevels] phase-A work counters (zeroed per call)
+    uint64_t *lbstate;           // [2 * lb_stride] split look-back state
+    size_t lb_stride;
     uint32_t *blkcnt;            // [2 * max grid] per-block counts
     int32_t *rank, *dom_in, *dom_out;  // outputs in original order (dom_* may be null)
     DevScalars *sc;
@@ -46,14 +50,22 @@ struct SortViews {
     Marker mark;
 };
 
+constexpr int kMaxHostLevels = 64;
+
 struct LaunchCfg {
     int num_cus;
-    int peel_blocks_per_cu;
+    int peel_blocks_per_cu;     // cooperative tail kernel
+    int phase_a_blocks_per_cu;  // per-level pairwise kernel
+    int host_levels;            // peeling levels enqueued as ordinary launches
 };
 
 hipError_t run_sort_stage(const SortViews &v, const LaunchCfg &cfg, hipStream_t s);
-// Largest cooperative grid the peeling kernel may use for this M (0 on error).
+
+// ---- peel.hip -------------------------------------------------------------
+hipError_t run_peel(const SortViews &v, const LaunchCfg &cfg, hipStream_t s);
+// Largest cooperative grid the peeling tail may use for this M (0 on error).
 int peel_max_blocks_per_cu(int M);
+size_t split_state_entries(int64_t N);
 
 // ---- select.hip -----------------------------------------------------------
 struct SelectViews {

@@ -58,10 +58,33 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *__res
     __shared__ uint32_t base_off[256];
     __shared__ uint32_t run[256];
     __shared__ uint32_t wc[kRsThreads / kWave][256];
+    __shared__ uint32_t scan_lds[17];
     const uint32_t tid = threadIdx.x;
     const uint32_t w = tid / kWave;
-    base_off[tid] = offs[(size_t)tid * nblocks + blockIdx.x];
+    // Offsets of this block's digits: all keys with a smaller digit, plus keys
+    // with the same digit in earlier blocks.  The histogram (digit-major) is
+    // read cooperatively and summed with LDS atomics.
+    base_off[tid] = 0;
     run[tid] = 0;
+    __syncthreads();
+    const int64_t nh = (int64_t)256 * nblocks;
+    for (int64_t x = tid; x < nh; x += kRsThreads) {
+        const uint32_t d = (uint32_t)(x / nblocks);
+        const uint32_t b = (uint32_t)(x - (int64_t)d * nblocks);
+        const uint32_t h = offs[x];
+        if (h) {
+            atomicAdd(&run[d], h);                      // digit total
+            if (b < blockIdx.x) atomicAdd(&base_off[d], h);  // same digit, earlier blocks
+        }
+    }
+    __syncthreads();
+    {
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(run[tid], scan_lds, &tot);
+        base_off[tid] += ex;
+    }
+    run[tid] = 0;
+    __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
     for (int it = 0; it < kRsItems; ++it) {
 #pragma unroll
@@ -114,8 +137,6 @@ void radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *k_alt, uint32_t 
     int passes = 0;
     for (int shift = 0; shift < nbits; shift += 8, ++passes) {
         hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kRsThreads), 0, s, ka, n, shift, temp, nb);
-        hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, temp, (int64_t)256 * nb,
-                           (uint32_t *)nullptr);
         hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kRsThreads), 0, s, ka, va, kb, vb, n,
                            shift, temp, nb);
         uint64_t *tk = ka; ka = kb; kb = tk;
