@@ -41,6 +41,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=60000)
     ap.add_argument("--check", action="store_true", help="verify one timed result (sampled)")
+    ap.add_argument("--assoc", default="fp32", choices=["fp32", "bf16"],
+                    help="association screening precision (re-scoring is float64 in both)")
+    ap.add_argument("--precision-report", action="store_true",
+                    help="instead of the throughput line: float32 vs bfloat16 association on the "
+                         "workload, errors against the float64 oracle and the phase times")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (three times), to scale "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -67,6 +72,66 @@ def cpu_baseline(name: str, N_full: int, n_sample: int):
                    f"'{name}' (same seed and shape recipe): {dt:.2f} s; scaled by (N/n)^2 to "
                    f"N={N_full}: {t_full:.1f} s per selection"),
     }
+
+
+def precision_report(args, w, objs, refs):
+    """One JSON line: association error of each screening precision against the
+    float64 oracle (on the GPU's own ranks, which both modes share), selection
+    agreement between the modes, and the association phase time of each."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2503_20286_amd as nsga3
+    modes = {"fp32": nsga3.ASSOC_FP32, "bf16": nsga3.ASSOC_BF16}
+    out = {}
+    res = {}
+    for name, mode in modes.items():
+        ctx = nsga3.Context(0, assoc=mode)
+        ctx.reserve(w.N, w.M, w.H)
+        r = nsga3.select(objs, refs, w.K, ctx=ctx)
+        for _ in range(args.warmup):
+            nsga3.select(objs, refs, w.K, ctx=ctx, out=r)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(args.steps):
+            nsga3.select(objs, refs, w.K, ctx=ctx, out=r)
+        torch.cuda.synchronize()
+        ms, calls = ctx.phase_times()
+        ctx.profile(False)
+        res[name] = {k: getattr(r, k).cpu().numpy() for k in ("selected", "rank", "niche", "dist")}
+        res[name]["info"] = r.info()
+        out[name] = {"associate_ms": ms[4] / calls, "total_ms": sum(ms) / calls}
+        ctx.close()
+    rank = res["fp32"]["rank"]
+    assert np.array_equal(rank, res["bf16"]["rank"])
+    l = res["fp32"]["info"].last_front
+    nz = oracle.normalize(w.objs, rank, l)
+    niche, dist, gap = oracle.associate(w.objs, rank, l, nz.z, nz.a, w.refs)
+    S = rank <= l
+    tie = S & (gap < 1e-6)
+    fpn = np.linalg.norm((w.objs.astype(np.float64) - nz.z) / nz.a, axis=1)
+    for name in modes:
+        g = res[name]
+        mism = (g["niche"] != niche) & S
+        dd = np.abs(g["dist"].astype(np.float64) - dist)[S]
+        out[name].update({
+            "niche_mismatch_outside_ties": int(np.sum(mism & ~tie)),
+            "niche_mismatch_at_ties": int(np.sum(mism & tie)),
+            "max_abs_dist_err": float(dd.max()),
+            "max_rel_dist_err": float((dd / np.maximum(1.0, fpn[S])).max()),
+            "near_ties_reported": g["info"].near_ties,
+        })
+    line = {
+        "metric": "association error vs float64 oracle, float32 and bfloat16 screening",
+        "workload": f"{args.workload}: N={w.N} M={w.M} H={w.H} K={w.K}",
+        "admitted_points": int(S.sum()),
+        "oracle_near_ties": int(tie.sum()),
+        "selection_identical_across_modes": bool(np.array_equal(res["fp32"]["selected"],
+                                                                res["bf16"]["selected"])),
+        "modes": out,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -98,7 +163,10 @@ def main():
     dev = torch.device("cuda:0")
     objs = torch.from_numpy(w.objs).to(dev)
     refs = torch.from_numpy(w.refs).to(dev)
-    ctx = nsga3.Context(0)
+    if args.precision_report:
+        precision_report(args, w, objs, refs)
+        return
+    ctx = nsga3.Context(0, assoc=nsga3.ASSOC_BF16 if args.assoc == "bf16" else nsga3.ASSOC_FP32)
     ctx.reserve(w.N, w.M, w.H)
     stream = torch.cuda.current_stream(dev)
     out = nsga3.select(objs, refs, w.K, ctx=ctx)
@@ -161,8 +229,8 @@ def main():
         "config": {
             "workload": f"{args.workload}: N={N} M={M} H={w.H} K={w.K}",
             "N": N, "M": M, "H": w.H, "K": w.K,
-            "compute": "u32 order-key compares (exact f32 dominance); f64 normalisation and "
-                       "re-scoring; f32 association screening",
+            "compute": "u32 order keys (exact f32 dominance, block bitsets); f64 normalisation "
+                       f"and re-scoring; {args.assoc} association screening",
             "parallelism": "single GPU",
         },
         "roofline": {

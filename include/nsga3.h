@@ -125,6 +125,54 @@ nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t 
                           int32_t *dom_in, int32_t *dom_out, nsga3_info *info,
                           hipStream_t stream);
 
+/*
+ * Batched selections: many independent problems (the islands or restarts of an
+ * optimizer farm), each with its own N, M, H and K, run by one graph launch.
+ * The fields of nsga3_problem mean what the arguments of nsga3_select mean;
+ * every pointer is DEVICE memory owned by the caller.
+ */
+typedef struct {
+    const float *objs;
+    int64_t N;
+    int32_t M;
+    const float *refs;
+    int32_t H;
+    int64_t K;
+    int32_t *selected;   /* required */
+    int32_t *rank;       /* optional (NULL) */
+    int32_t *niche;      /* optional */
+    float *dist;         /* optional */
+    int32_t *dom_in;     /* optional */
+    int32_t *dom_out;    /* optional */
+    nsga3_info *info;    /* optional */
+} nsga3_problem;
+
+typedef struct nsga3_plan nsga3_plan;
+
+/*
+ * Build a plan for B problems (probs: host array of B descriptors).  The plan
+ * allocates its own workspaces, picks per-problem launch shapes (see
+ * NSGA3_TUNE below), and captures every selection into one HIP graph whose
+ * branches run problems concurrently.  Synchronous; allocates.  The buffer
+ * pointers are baked into the graph: the caller keeps them alive and may
+ * rewrite their contents between launches.  Results of a launch are
+ * identical to running nsga3_select on each problem.
+ * Errors: NSGA3_E_INVALID for a bad descriptor (nothing is built),
+ * NSGA3_E_NOMEM / NSGA3_E_HIP when allocation or capture fails.
+ */
+nsga3_status nsga3_plan_create(nsga3_ctx *ctx, const nsga3_problem *probs, int32_t B,
+                               nsga3_plan **out);
+
+/* Launch the plan's graph on `stream` (asynchronous). */
+nsga3_status nsga3_plan_launch(nsga3_plan *plan, hipStream_t stream);
+
+/* Number of concurrent branches and of graph nodes (host query; either may be NULL). */
+nsga3_status nsga3_plan_info(const nsga3_plan *plan, int32_t *branches, int64_t *nodes);
+
+/* Free the plan (graph, workspaces).  The caller must make sure no launch of
+ * the plan is still running.  NULL is ignored. */
+void nsga3_plan_destroy(nsga3_plan *plan);
+
 /* Phases of one nsga3_select call, for nsga3_phase_times. */
 #define NSGA3_NUM_PHASES 6
 /*   0  keys, ideal point, presort by key sum            (Alg. S.5 first step; sort prerequisite)

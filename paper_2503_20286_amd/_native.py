@@ -42,6 +42,15 @@ class _Options(ctypes.Structure):
                 ("max_workspace_bytes", ctypes.c_size_t)]
 
 
+class _Problem(ctypes.Structure):
+    _fields_ = [("objs", ctypes.c_void_p), ("N", ctypes.c_int64), ("M", ctypes.c_int32),
+                ("refs", ctypes.c_void_p), ("H", ctypes.c_int32), ("K", ctypes.c_int64),
+                ("selected", ctypes.c_void_p), ("rank", ctypes.c_void_p),
+                ("niche", ctypes.c_void_p), ("dist", ctypes.c_void_p),
+                ("dom_in", ctypes.c_void_p), ("dom_out", ctypes.c_void_p),
+                ("info", ctypes.c_void_p)]
+
+
 INFO_FIELDS = ("status", "last_front", "num_fronts", "last_front_size", "num_from_last",
                "intercept_fallback", "near_ties", "reserved")
 
@@ -77,6 +86,14 @@ def load():
         L.nsga3_profile.restype = ctypes.c_int
         L.nsga3_phase_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.nsga3_phase_times.restype = ctypes.c_int
+        L.nsga3_plan_create.argtypes = [P, ctypes.POINTER(_Problem), i32, ctypes.POINTER(P)]
+        L.nsga3_plan_create.restype = ctypes.c_int
+        L.nsga3_plan_launch.argtypes = [P, P]
+        L.nsga3_plan_launch.restype = ctypes.c_int
+        L.nsga3_plan_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.nsga3_plan_info.restype = ctypes.c_int
+        L.nsga3_plan_destroy.argtypes = [P]
+        L.nsga3_plan_destroy.restype = None
         L.nsga3_version.argtypes = []
         L.nsga3_version.restype = ctypes.c_int32
         _lib = L
@@ -248,3 +265,83 @@ def select(objs, refs, K: int, *, ctx: Optional[Context] = None, assoc: int = AS
     if rc != 0:
         raise NativeError("nsga3_select", rc, ctx._lib)
     return out
+
+
+def _alloc_outputs(N, K, dev, want_counts=True, want_dist=True):
+    import torch
+    i32 = dict(dtype=torch.int32, device=dev)
+    return Selection(
+        selected=torch.empty(int(K), **i32),
+        rank=torch.empty(N, **i32),
+        niche=torch.empty(N, **i32),
+        dist=torch.empty(N, dtype=torch.float32, device=dev) if want_dist else None,
+        dom_in=torch.empty(N, **i32) if want_counts else None,
+        dom_out=torch.empty(N, **i32) if want_counts else None,
+        info_raw=torch.zeros(8, **i32),
+    )
+
+
+class Plan:
+    """A batched plan: many independent selections captured into one HIP graph.
+
+    ``problems`` is a list of (objs, refs, K) with device float32 tensors; the
+    plan allocates one output Selection per problem (``results``) and keeps
+    every buffer alive.  ``launch()`` replays the graph; rewrite the input
+    tensors in place to select on new data."""
+
+    def __init__(self, problems, ctx: Optional[Context] = None, want_counts: bool = True,
+                 want_dist: bool = True):
+        import torch
+        if not problems:
+            raise ValueError("empty batch")
+        dev = problems[0][0].device
+        self.ctx = ctx if ctx is not None else default_context(
+            dev.index if dev.index is not None else torch.cuda.current_device())
+        self._lib = self.ctx._lib
+        self.inputs = []
+        self.results = []
+        descs = (_Problem * len(problems))()
+        for b, (objs, refs, K) in enumerate(problems):
+            _check_tensor(objs, "objs", 2)
+            _check_tensor(refs, "refs", 2)
+            N, M = objs.shape
+            out = _alloc_outputs(N, K, dev, want_counts, want_dist)
+            self.inputs.append((objs, refs))
+            self.results.append(out)
+
+            def ptr(t):
+                return None if t is None else t.data_ptr()
+            descs[b] = _Problem(ptr(objs), int(N), int(M), ptr(refs), int(refs.shape[0]), int(K),
+                                ptr(out.selected), ptr(out.rank), ptr(out.niche), ptr(out.dist),
+                                ptr(out.dom_in), ptr(out.dom_out), ptr(out.info_raw))
+        h = ctypes.c_void_p()
+        rc = self._lib.nsga3_plan_create(self.ctx.handle, descs, len(problems), ctypes.byref(h))
+        if rc != 0:
+            raise NativeError("nsga3_plan_create", rc, self._lib)
+        self._h = h
+
+    def info(self):
+        b = ctypes.c_int32()
+        n = ctypes.c_int64()
+        rc = self._lib.nsga3_plan_info(self._h, ctypes.byref(b), ctypes.byref(n))
+        if rc != 0:
+            raise NativeError("nsga3_plan_info", rc, self._lib)
+        return {"branches": b.value, "nodes": n.value}
+
+    def launch(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        rc = self._lib.nsga3_plan_launch(self._h, ctypes.c_void_p(s.cuda_stream))
+        if rc != 0:
+            raise NativeError("nsga3_plan_launch", rc, self._lib)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.nsga3_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass

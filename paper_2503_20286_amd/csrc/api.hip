@@ -4,12 +4,25 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
 #include "kernels.h"
 
 using namespace nsga3;
+
+struct nsga3_plan {
+    int device = 0;
+    int branches = 0;
+    int64_t nodes = 0;
+    std::vector<void *> ws;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 struct nsga3_ctx {
     int device;
@@ -20,6 +33,9 @@ struct nsga3_ctx {
     size_t ws_bytes;
     bool profiling;
     int phase_a_bpc;
+    bool bitsets;
+    bool tail_block;
+    int fixed_levels;               // > 0: always enqueue this many peeling levels
     volatile int32_t *last_fronts;  // pinned: front count of the latest call
     std::vector<hipEvent_t> ev_pool;   // NSGA3_NUM_PHASES + 1 events per recorded call
     size_t ev_used;
@@ -30,12 +46,15 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kMaxPeelBlocksPerCu = 4;
 constexpr int kDefaultHostLevels = 24;
+constexpr int kPlanBranches = 8;   // concurrent graph branches of a batched plan
+constexpr int kPlanLevels = 8;     // peeling levels enqueued per problem in a plan
 
 struct Layout {
     size_t skey, skey_alt, sval, sval_alt, temp, recs, runstart, dom_in_s, dom_out_s, rank_s;
     size_t fk0, fk1, uk0, uk1, urun0, urun1, ucnt0, ucnt1, fsize, usize, work, lbstate, blkcnt;
+    size_t runend, tabs_all, tabs_lvl;
     size_t lb_stride;
-    size_t rank, niche, dist64, rhat64, rhat32, p_asf, p_idx, p_nad;
+    size_t rank, niche, dist64, rhat64, rhat32, rhat16, p_asf, p_idx, p_nad;
     size_t rho, bcount, bstart, bcursor, bd, bi, selflag, sc, bar;
     size_t total;
 };
@@ -62,6 +81,9 @@ Layout layout_for(int64_t N, int M, int H, int max_grid) {
     L.temp = bump(c, temp);
     L.recs = bump(c, 4 * n * MP);
     L.runstart = bump(c, 4 * n);
+    L.runend = bump(c, 4 * n);
+    L.tabs_all = bump(c, bit_tables_bytes(N, M));
+    L.tabs_lvl = bump(c, bit_tables_bytes(N, M));
     L.dom_in_s = bump(c, 4 * n);
     L.dom_out_s = bump(c, 4 * n);
     L.rank_s = bump(c, 4 * n);
@@ -84,6 +106,7 @@ Layout layout_for(int64_t N, int M, int H, int max_grid) {
     L.dist64 = bump(c, 8 * n);
     L.rhat64 = bump(c, 8 * (size_t)H * M);
     L.rhat32 = bump(c, 4 * (size_t)H * M);
+    L.rhat16 = bump(c, 2 * (size_t)((H + 31) / 32 * 32) * (M <= 8 ? 8 : 16));
     L.p_asf = bump(c, 8 * (size_t)nparts * M);
     L.p_idx = bump(c, 4 * (size_t)nparts * M);
     L.p_nad = bump(c, 8 * (size_t)nparts * M);
@@ -145,7 +168,7 @@ struct PhaseMarks {
     nsga3_ctx *ctx;
     hipStream_t s;
     bool on;
-    PhaseMarks(nsga3_ctx *c, hipStream_t st) : ctx(c), s(st), on(c->profiling) {
+    PhaseMarks(nsga3_ctx *c, hipStream_t st) : ctx(c), s(st), on(c && c->profiling) {
         if (on && c->ev_used + NSGA3_NUM_PHASES + 1 > c->ev_pool.size()) {
             for (int q = 0; q <= NSGA3_NUM_PHASES; ++q) {
                 hipEvent_t e;
@@ -158,6 +181,146 @@ struct PhaseMarks {
         if (on) (void)hipEventRecord(ctx->ev_pool[ctx->ev_used++], s);
     }
 };
+
+
+LaunchCfg ctx_cfg(const nsga3_ctx *ctx, int M) {
+    LaunchCfg cfg;
+    cfg.num_cus = ctx->num_cus;
+    cfg.peel_blocks_per_cu = ctx->peel_bpc[M];
+    cfg.phase_a_blocks_per_cu = ctx->phase_a_bpc;
+    cfg.bitsets = ctx->bitsets;
+    cfg.tail_block = ctx->tail_block;
+    // enqueue one more level than the previous call needed (its front count
+    // arrives asynchronously in pinned memory; a stale value only shifts work
+    // between the enqueued levels and the tail)
+    const int prev = ctx->last_fronts ? *ctx->last_fronts : 0;
+    int lv = prev > 0 ? prev + 1 : kDefaultHostLevels;
+    if (ctx->fixed_levels > 0) lv = ctx->fixed_levels;
+    if (lv > kMaxHostLevels) lv = kMaxHostLevels;
+    if (lv < 1) lv = 1;
+    cfg.host_levels = lv;
+    return cfg;
+}
+
+struct EnqArgs {
+    char *ws;
+    LaunchCfg cfg;
+    int assoc;
+    nsga3_ctx *marks;                 // record phase events into this context, or null
+    volatile int32_t *last_fronts;    // pinned slot for the front count, or null
+};
+
+// Enqueues one whole selection on `stream` using the workspace at a.ws (sized
+// by layout_for for the problem).  Allocates nothing; safe to capture.
+hipError_t enqueue_select(const EnqArgs &a, const nsga3_problem &p, hipStream_t stream) {
+    const float *objs = p.objs, *refs = p.refs;
+    const int64_t N = p.N, K = p.K;
+    const int32_t M = p.M, H = p.H;
+    int32_t *selected = p.selected, *rank = p.rank, *niche = p.niche;
+    float *dist = p.dist;
+    int32_t *dom_in = p.dom_in, *dom_out = p.dom_out;
+    nsga3_info *info = p.info;
+    const Layout L = layout_for(N, M, H, kGridCap);
+    char *w = a.ws;
+#define WS(T, f) reinterpret_cast<T *>(w + L.f)
+    DevScalars *sc = WS(DevScalars, sc);
+    int32_t *rank_o = rank ? rank : WS(int32_t, rank);
+    int32_t *niche_o = niche ? niche : WS(int32_t, niche);
+
+    PhaseMarks marks(a.marks, stream);
+    Marker mk;
+    mk.fn = [](void *x) { static_cast<PhaseMarks *>(x)->mark(); };
+    mk.arg = &marks;
+    marks.mark();
+    int32_t *zero_p[] = {WS(int32_t, dom_in_s), WS(int32_t, dom_out_s), WS(int32_t, rho),
+                         WS(int32_t, bcount), WS(int32_t, bar), WS(int32_t, work),
+                         WS(int32_t, lbstate)};
+    const int64_t zero_n[] = {N, N, H, H, (int64_t)(sizeof(GridBar) / sizeof(int32_t)),
+                              kMaxHostLevels, (int64_t)(2 * L.lb_stride)};
+    hipError_t e = run_init(sc, zero_p, zero_n, 7, stream);
+    if (e == hipSuccess)
+        e = run_refs(refs, H, M, WS(double, rhat64), WS(float, rhat32), WS(uint16_t, rhat16), sc,
+                     stream);
+
+    SortViews sv;
+    sv.objs = objs;
+    sv.N = N;
+    sv.M = M;
+    sv.K = K;
+    sv.skey = WS(uint64_t, skey);
+    sv.skey_alt = WS(uint64_t, skey_alt);
+    sv.sval = WS(uint32_t, sval);
+    sv.sval_alt = WS(uint32_t, sval_alt);
+    sv.temp = WS(uint32_t, temp);
+    sv.recs = WS(uint32_t, recs);
+    sv.runstart = WS(int32_t, runstart);
+    sv.runend = WS(int32_t, runend);
+    sv.tabs_all = WS(uint32_t, tabs_all);
+    sv.tabs_lvl = WS(uint32_t, tabs_lvl);
+    sv.dom_in_s = WS(int32_t, dom_in_s);
+    sv.dom_out_s = WS(int32_t, dom_out_s);
+    sv.rank_s = WS(int32_t, rank_s);
+    sv.fk[0] = WS(uint32_t, fk0);
+    sv.fk[1] = WS(uint32_t, fk1);
+    sv.uk[0] = WS(uint32_t, uk0);
+    sv.uk[1] = WS(uint32_t, uk1);
+    sv.urun[0] = WS(int32_t, urun0);
+    sv.urun[1] = WS(int32_t, urun1);
+    sv.ucnt[0] = WS(int32_t, ucnt0);
+    sv.ucnt[1] = WS(int32_t, ucnt1);
+    sv.fsize = WS(int32_t, fsize);
+    sv.usize = WS(int32_t, usize);
+    sv.work = WS(uint32_t, work);
+    sv.lbstate = WS(uint64_t, lbstate);
+    sv.lb_stride = L.lb_stride;
+    sv.blkcnt = WS(uint32_t, blkcnt);
+    sv.rank = rank_o;
+    sv.dom_in = dom_in;
+    sv.dom_out = dom_out;
+    sv.sc = sc;
+    sv.bar = WS(GridBar, bar);
+    sv.mark = mk;
+    const LaunchCfg &cfg = a.cfg;
+    if (e == hipSuccess) e = run_sort_stage(sv, cfg, stream);
+    if (e == hipSuccess && a.last_fronts)
+        e = hipMemcpyAsync((void *)a.last_fronts, &sc->num_fronts, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, stream);
+
+    SelectViews xv;
+    xv.objs = objs;
+    xv.N = N;
+    xv.M = M;
+    xv.refs = refs;
+    xv.H = H;
+    xv.K = K;
+    xv.rank = rank_o;
+    xv.niche = niche_o;
+    xv.dist = dist;
+    xv.dist64 = WS(double, dist64);
+    xv.rhat64 = WS(double, rhat64);
+    xv.rhat32 = WS(float, rhat32);
+    xv.rhat16 = WS(uint16_t, rhat16);
+    xv.p_asf = WS(double, p_asf);
+    xv.p_idx = WS(int32_t, p_idx);
+    xv.p_nad = WS(double, p_nad);
+    xv.rho = WS(int32_t, rho);
+    xv.bcount = WS(int32_t, bcount);
+    xv.bstart = WS(int32_t, bstart);
+    xv.bcursor = WS(int32_t, bcursor);
+    xv.bd = WS(double, bd);
+    xv.bi = WS(int32_t, bi);
+    xv.selflag = WS(uint8_t, selflag);
+    xv.temp = WS(uint32_t, temp);
+    xv.selected = selected;
+    xv.info = info;
+    xv.sc = sc;
+    xv.assoc_mode = a.assoc;
+    xv.mark = mk;
+#undef WS
+    if (e == hipSuccess) e = run_select_stage(xv, stream);
+    if (e != hipSuccess) (void)hipGetLastError();
+    return e;
+}
 
 }  // namespace
 
@@ -229,6 +392,19 @@ nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt)
     c->profiling = false;
     c->ev_used = 0;
     c->phase_a_bpc = 8;
+    c->fixed_levels = 0;
+    // NSGA3_PAIRWISE=1 selects the pairwise-compare dominance kernels instead
+    // of the block-bitset ones (same results; kept for comparison)
+    c->bitsets = true;
+    if (const char *e = getenv("NSGA3_PAIRWISE")) c->bitsets = atoi(e) == 0;
+    // NSGA3_TAIL_BLOCK=1: finish peeling in one workgroup instead of the
+    // cooperative grid (the form captured graphs use; same results)
+    c->tail_block = false;
+    if (const char *e = getenv("NSGA3_TAIL_BLOCK")) c->tail_block = atoi(e) != 0;
+    if (const char *e = getenv("NSGA3_HOST_LEVELS")) {
+        const int v = atoi(e);
+        if (v >= 1 && v <= kMaxHostLevels) c->fixed_levels = v;
+    }
     if (const char *e = getenv("NSGA3_PHASE_A_BLOCKS_PER_CU")) {
         const int v = atoi(e);
         if (v >= 1 && v <= 32) c->phase_a_bpc = v;
@@ -301,115 +477,151 @@ nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t 
     const Layout L = layout_for(N, M, H, kGridCap);
     nsga3_status st = ensure_ws(ctx, L.total);
     if (st != NSGA3_OK) return st;
-    char *w = (char *)ctx->ws;
-#define WS(T, f) reinterpret_cast<T *>(w + L.f)
-    DevScalars *sc = WS(DevScalars, sc);
-    int32_t *rank_o = rank ? rank : WS(int32_t, rank);
-    int32_t *niche_o = niche ? niche : WS(int32_t, niche);
+    EnqArgs a;
+    a.ws = (char *)ctx->ws;
+    a.cfg = ctx_cfg(ctx, M);
+    a.assoc = (int)ctx->opt.assoc;
+    a.marks = ctx->profiling ? ctx : nullptr;
+    a.last_fronts = ctx->last_fronts;
+    const nsga3_problem p = {objs, N, M, refs, H, K, selected, rank, niche, dist,
+                             dom_in, dom_out, info};
+    return enqueue_select(a, p, stream) == hipSuccess ? NSGA3_OK : NSGA3_E_HIP;
+}
 
-    PhaseMarks marks(ctx, stream);
-    Marker mk;
-    mk.fn = [](void *a) { static_cast<PhaseMarks *>(a)->mark(); };
-    mk.arg = &marks;
-    marks.mark();
-    int32_t *zero_p[] = {WS(int32_t, dom_in_s), WS(int32_t, dom_out_s), WS(int32_t, rho),
-                         WS(int32_t, bcount), WS(int32_t, bar), WS(int32_t, work),
-                         WS(int32_t, lbstate)};
-    const int64_t zero_n[] = {N, N, H, H, (int64_t)(sizeof(GridBar) / sizeof(int32_t)),
-                              kMaxHostLevels, (int64_t)(2 * L.lb_stride)};
-    hipError_t e = run_init(sc, zero_p, zero_n, 7, stream);
-    if (e == hipSuccess) e = run_refs(refs, H, M, WS(double, rhat64), WS(float, rhat32), sc, stream);
+static bool problem_ok(const nsga3_problem &p) {
+    return p.objs && p.refs && p.selected && sizes_ok(p.N, p.M, p.H) && p.K >= 1 && p.K <= p.N;
+}
 
-    SortViews sv;
-    sv.objs = objs;
-    sv.N = N;
-    sv.M = M;
-    sv.K = K;
-    sv.skey = WS(uint64_t, skey);
-    sv.skey_alt = WS(uint64_t, skey_alt);
-    sv.sval = WS(uint32_t, sval);
-    sv.sval_alt = WS(uint32_t, sval_alt);
-    sv.temp = WS(uint32_t, temp);
-    sv.recs = WS(uint32_t, recs);
-    sv.runstart = WS(int32_t, runstart);
-    sv.dom_in_s = WS(int32_t, dom_in_s);
-    sv.dom_out_s = WS(int32_t, dom_out_s);
-    sv.rank_s = WS(int32_t, rank_s);
-    sv.fk[0] = WS(uint32_t, fk0);
-    sv.fk[1] = WS(uint32_t, fk1);
-    sv.uk[0] = WS(uint32_t, uk0);
-    sv.uk[1] = WS(uint32_t, uk1);
-    sv.urun[0] = WS(int32_t, urun0);
-    sv.urun[1] = WS(int32_t, urun1);
-    sv.ucnt[0] = WS(int32_t, ucnt0);
-    sv.ucnt[1] = WS(int32_t, ucnt1);
-    sv.fsize = WS(int32_t, fsize);
-    sv.usize = WS(int32_t, usize);
-    sv.work = WS(uint32_t, work);
-    sv.lbstate = WS(uint64_t, lbstate);
-    sv.lb_stride = L.lb_stride;
-    sv.blkcnt = WS(uint32_t, blkcnt);
-    sv.rank = rank_o;
-    sv.dom_in = dom_in;
-    sv.dom_out = dom_out;
-    sv.sc = sc;
-    sv.bar = WS(GridBar, bar);
-    sv.mark = mk;
-    LaunchCfg cfg;
-    cfg.num_cus = ctx->num_cus;
-    cfg.peel_blocks_per_cu = ctx->peel_bpc[M];
-    cfg.phase_a_blocks_per_cu = ctx->phase_a_bpc;
-    {
-        // enqueue one more level than the previous call needed (its front
-        // count arrives asynchronously in pinned memory; a stale value only
-        // shifts work between the enqueued levels and the cooperative tail)
-        const int prev = ctx->last_fronts ? *ctx->last_fronts : 0;
-        int lv = prev > 0 ? prev + 1 : kDefaultHostLevels;
-        if (lv > kMaxHostLevels) lv = kMaxHostLevels;
-        if (lv < 1) lv = 1;
-        cfg.host_levels = lv;
+static void plan_free(nsga3_plan *pl) {
+    if (!pl) return;
+    DeviceGuard g(pl->device);
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    for (hipEvent_t e : pl->events) (void)hipEventDestroy(e);
+    for (hipStream_t st : pl->streams) (void)hipStreamDestroy(st);
+    if (pl->cap) (void)hipStreamDestroy(pl->cap);
+    for (void *w : pl->ws)
+        if (w) (void)hipFree(w);
+    delete pl;
+}
+
+nsga3_status nsga3_plan_create(nsga3_ctx *ctx, const nsga3_problem *probs, int32_t B,
+                               nsga3_plan **out) {
+    if (!ctx || !probs || !out || B < 1) return NSGA3_E_INVALID;
+    *out = nullptr;
+    for (int32_t b = 0; b < B; ++b)
+        if (!problem_ok(probs[b])) return NSGA3_E_INVALID;
+    DeviceGuard g(ctx->device);
+    nsga3_plan *pl = new (std::nothrow) nsga3_plan();
+    if (!pl) return NSGA3_E_NOMEM;
+    pl->device = ctx->device;
+    int nbr = kPlanBranches;
+    if (const char *e = getenv("NSGA3_PLAN_BRANCHES")) {
+        const int v = atoi(e);
+        if (v >= 1 && v <= 64) nbr = v;
     }
-    if (e == hipSuccess) e = run_sort_stage(sv, cfg, stream);
-    if (e == hipSuccess && ctx->last_fronts)
-        e = hipMemcpyAsync((void *)ctx->last_fronts, &sc->num_fronts, sizeof(int32_t),
-                           hipMemcpyDeviceToHost, stream);
+    if (nbr > B) nbr = B;
+    pl->branches = nbr;
+    int levels = kPlanLevels;
+    if (const char *e = getenv("NSGA3_PLAN_LEVELS")) {
+        const int v = atoi(e);
+        if (v >= 1 && v <= kMaxHostLevels) levels = v;
+    }
+    // balance the branches: largest problems first, each to the least loaded branch
+    std::vector<int32_t> order(B);
+    for (int32_t b = 0; b < B; ++b) order[b] = b;
+    auto cost = [&](int32_t b) { return (double)probs[b].N * (double)probs[b].N * probs[b].M; };
+    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
+    std::vector<std::vector<int32_t>> members(nbr);
+    std::vector<double> load(nbr, 0.0);
+    std::vector<size_t> need(nbr, 0);
+    for (int32_t b : order) {
+        int best = 0;
+        for (int q = 1; q < nbr; ++q)
+            if (load[q] < load[best]) best = q;
+        members[best].push_back(b);
+        load[best] += cost(b);
+        const size_t n = layout_for(probs[b].N, probs[b].M, probs[b].H, kGridCap).total;
+        if (n > need[best]) need[best] = n;
+    }
+    for (int q = 0; q < nbr; ++q) std::sort(members[q].begin(), members[q].end());
+    nsga3_status st = NSGA3_OK;
+    hipError_t e = hipSuccess;
+    pl->ws.assign(nbr, nullptr);
+    for (int q = 0; q < nbr && st == NSGA3_OK; ++q) {
+        if (ctx->opt.max_workspace_bytes && need[q] > ctx->opt.max_workspace_bytes) st = NSGA3_E_NOMEM;
+        else if (hipMalloc(&pl->ws[q], need[q]) != hipSuccess) { (void)hipGetLastError(); st = NSGA3_E_NOMEM; }
+    }
+    if (st == NSGA3_OK) {
+        e = hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking);
+        for (int q = 0; q < nbr && e == hipSuccess; ++q) {
+            hipStream_t bs;
+            e = hipStreamCreateWithFlags(&bs, hipStreamNonBlocking);
+            if (e == hipSuccess) pl->streams.push_back(bs);
+        }
+        for (int q = 0; q <= nbr && e == hipSuccess; ++q) {
+            hipEvent_t ev;
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) pl->events.push_back(ev);
+        }
+        if (e != hipSuccess) st = NSGA3_E_HIP;
+    }
+    if (st == NSGA3_OK) {
+        e = hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) e = hipEventRecord(pl->events[nbr], pl->cap);
+        for (int q = 0; q < nbr && e == hipSuccess; ++q) {
+            e = hipStreamWaitEvent(pl->streams[q], pl->events[nbr], 0);
+            for (int32_t b : members[q]) {
+                if (e != hipSuccess) break;
+                EnqArgs a;
+                a.ws = (char *)pl->ws[q];
+                a.cfg = ctx_cfg(ctx, probs[b].M);
+                a.cfg.tail_block = true;       // cooperative launches cannot be captured
+                a.cfg.host_levels = levels;
+                a.assoc = (int)ctx->opt.assoc;
+                a.marks = nullptr;
+                a.last_fronts = nullptr;
+                e = enqueue_select(a, probs[b], pl->streams[q]);
+            }
+            if (e == hipSuccess) e = hipEventRecord(pl->events[q], pl->streams[q]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(pl->cap, pl->events[q], 0);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(pl->cap, &graph);
+        if (e == hipSuccess) e = e2;
+        pl->graph = graph;
+        if (e == hipSuccess) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) {
+            size_t nn = 0;
+            if (hipGraphGetNodes(pl->graph, nullptr, &nn) == hipSuccess) pl->nodes = (int64_t)nn;
+        }
+        if (e != hipSuccess) { (void)hipGetLastError(); st = NSGA3_E_HIP; }
+    }
+    if (st != NSGA3_OK) {
+        plan_free(pl);
+        return st;
+    }
+    *out = pl;
+    return NSGA3_OK;
+}
 
-    SelectViews xv;
-    xv.objs = objs;
-    xv.N = N;
-    xv.M = M;
-    xv.refs = refs;
-    xv.H = H;
-    xv.K = K;
-    xv.rank = rank_o;
-    xv.niche = niche_o;
-    xv.dist = dist;
-    xv.dist64 = WS(double, dist64);
-    xv.rhat64 = WS(double, rhat64);
-    xv.rhat32 = WS(float, rhat32);
-    xv.p_asf = WS(double, p_asf);
-    xv.p_idx = WS(int32_t, p_idx);
-    xv.p_nad = WS(double, p_nad);
-    xv.rho = WS(int32_t, rho);
-    xv.bcount = WS(int32_t, bcount);
-    xv.bstart = WS(int32_t, bstart);
-    xv.bcursor = WS(int32_t, bcursor);
-    xv.bd = WS(double, bd);
-    xv.bi = WS(int32_t, bi);
-    xv.selflag = WS(uint8_t, selflag);
-    xv.temp = WS(uint32_t, temp);
-    xv.selected = selected;
-    xv.info = info;
-    xv.sc = sc;
-    xv.assoc_mode = (int)ctx->opt.assoc;
-    xv.mark = mk;
-#undef WS
-    if (e == hipSuccess) e = run_select_stage(xv, stream);
-    if (e != hipSuccess) {
+nsga3_status nsga3_plan_launch(nsga3_plan *plan, hipStream_t stream) {
+    if (!plan || !plan->exec) return NSGA3_E_INVALID;
+    DeviceGuard g(plan->device);
+    if (hipGraphLaunch(plan->exec, stream) != hipSuccess) {
         (void)hipGetLastError();
         return NSGA3_E_HIP;
     }
     return NSGA3_OK;
 }
+
+nsga3_status nsga3_plan_info(const nsga3_plan *plan, int32_t *branches, int64_t *nodes) {
+    if (!plan) return NSGA3_E_INVALID;
+    if (branches) *branches = plan->branches;
+    if (nodes) *nodes = plan->nodes;
+    return NSGA3_OK;
+}
+
+void nsga3_plan_destroy(nsga3_plan *plan) { plan_free(plan); }
 
 }  // extern "C"

@@ -1,0 +1,385 @@
+// Block-bitset dominance kernels (see bitdom.h): table construction, the
+// forward pass (each lane a later point j; counts the members of earlier
+// blocks that dominate j -- in-degrees, or the peeling decrements of one
+// front) and the backward pass (each lane an earlier point i; counts the
+// members of later blocks that i dominates -- out-degrees).
+//
+// Dominance is Listing 1 / Eq. (6) on order keys (minimisation).  Candidates
+// are restricted by the presort: an earlier point i can dominate j only when
+// i lies before the run of points sharing j's key sum (identical rows and
+// equal-sum points never dominate each other).
+#include "bitdom.h"
+#include "kernels.h"
+#include "prims.h"
+
+namespace nsga3 {
+
+constexpr int kFwdThreads = 256;
+constexpr int kTJ = 2;                            // points per lane
+constexpr int kTileJ = kFwdThreads * kTJ;         // points per work item
+constexpr int kLdsTabDwords = 8704;               // 34 KiB of tables per work item
+
+template <int M>
+__host__ __device__ constexpr int blocks_per_chunk() {
+    return kLdsTabDwords / blk_stride(M) < 1 ? 1 : kLdsTabDwords / blk_stride(M);
+}
+
+// ---------------------------------------------------------------------------
+// Tables: one wave per block of 64 consecutive list entries.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(64) void k_build_blocks(const uint32_t *__restrict__ rec,
+                                                     int32_t n_static,
+                                                     const int32_t *__restrict__ n_dev,
+                                                     uint32_t *__restrict__ tabs,
+                                                     const DevScalars *__restrict__ sc) {
+    constexpr int MP = rec_stride(M);
+    constexpr int TS = blk_stride(M);
+    __shared__ int32_t inv[kBlk];
+    if (sc->err) return;
+    const int32_t n = n_static >= 0 ? n_static : *n_dev;
+    const int32_t b = blockIdx.x;
+    if ((int64_t)b * kBlk >= n) return;
+    const int l = threadIdx.x;
+    const int32_t e = b * kBlk + l;
+    const bool valid = e < n;
+    const int32_t nmem = min(kBlk, n - b * kBlk);
+    uint32_t *T = tabs + (size_t)b * TS;
+    const int32_t pos = valid ? (int32_t)rec[(size_t)e * MP + M] : 0x7fffffff;
+    T[blk_pos_off() + l] = (uint32_t)pos;
+    if (l == 0) {
+        T[0] = (uint32_t)pos;
+        T[1] = rec[(size_t)(b * kBlk + nmem - 1) * MP + M];
+        T[2] = (uint32_t)nmem;
+        T[3] = 0;
+    }
+    for (int k = 0; k < M; ++k) {
+        const uint32_t key = valid ? rec[(size_t)e * MP + k] : 0xffffffffu;
+        uint32_t rank = 0;
+        for (int m = 0; m < kBlk; ++m) {
+            const uint32_t o = __shfl(key, m, 64);
+            rank += (o < key || (o == key && m < l)) ? 1u : 0u;
+        }
+        T[blk_key_off(k) + rank] = key;
+        inv[rank] = l;
+        __syncthreads();
+        const int mem = inv[l];
+        uint64_t bit = (mem < nmem) ? (1ull << mem) : 0ull;
+        for (int o = 1; o < kBlk; o <<= 1) {
+            const uint64_t t = __shfl_up(bit, o, 64);
+            if (l >= o) bit |= t;
+        }
+        uint64_t *pm = reinterpret_cast<uint64_t *>(T + blk_pm_off(M, k));
+        pm[l + 1] = bit;
+        if (l == 0) pm[0] = 0ull;
+        __syncthreads();
+    }
+}
+
+// Stage `nb` consecutive tables into LDS.
+template <int M>
+__device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__restrict__ tabs,
+                                             int32_t b0, int32_t nb) {
+    constexpr int TS = blk_stride(M);
+    const uint4 *src = reinterpret_cast<const uint4 *>(tabs + (size_t)b0 * TS);
+    uint4 *dst = reinterpret_cast<uint4 *>(lds);
+    const int nvec = nb * (TS / 4);
+    for (int q = threadIdx.x; q < nvec; q += kFwdThreads) dst[q] = src[q];
+}
+
+// Forward: for each of the wave's kTJ x 64 points j (keys kj, run starts run),
+// add the number of members of the staged blocks that dominate j.
+template <int M>
+__device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32_t run_lo,
+                                           int32_t run_hi, const uint32_t (&kj)[kTJ][M],
+                                           const int32_t (&run)[kTJ], int32_t (&cnt)[kTJ]) {
+    constexpr int TS = blk_stride(M);
+    for (int32_t b = 0; b < nb; ++b) {
+        const uint32_t *T = lt + b * TS;
+        const int32_t bmin = (int32_t)T[0];
+        const int32_t bmax = (int32_t)T[1];
+        if (bmin >= run_hi) break;  // later blocks start later still
+        const bool full = bmax < run_lo;
+#pragma unroll
+        for (int t = 0; t < kTJ; ++t) {
+            uint64_t m = ~0ull;
+            if (!full) {
+                if (run[t] <= bmin) m = 0ull;
+                else if (run[t] <= bmax)
+                    m = low_bits(count_pos_lt64(reinterpret_cast<const int32_t *>(T + blk_pos_off()),
+                                                run[t]));
+            }
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const uint32_t c = count_le64(T + blk_key_off(k), kj[t][k]);
+                m &= reinterpret_cast<const uint64_t *>(T + blk_pm_off(M, k))[c];
+            }
+            cnt[t] += __popcll(m);
+        }
+    }
+}
+
+// Loads the wave's points (records with MP stride, run starts) into registers.
+template <int M>
+__device__ __forceinline__ void load_points(const uint32_t *__restrict__ jrec,
+                                            const int32_t *__restrict__ jrun, int32_t nj,
+                                            int32_t jbase, int lane, uint32_t (&kj)[kTJ][M],
+                                            int32_t (&run)[kTJ]) {
+    constexpr int MP = rec_stride(M);
+#pragma unroll
+    for (int t = 0; t < kTJ; ++t) {
+        const int32_t q = jbase + t * kWave + lane;
+        if (q < nj) {
+#pragma unroll
+            for (int k = 0; k < M; ++k) kj[t][k] = jrec[(size_t)q * MP + k];
+            run[t] = jrun[q];
+        } else {
+#pragma unroll
+            for (int k = 0; k < M; ++k) kj[t][k] = 0u;  // below every key: dominated by nothing
+            run[t] = 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// In-degrees over all points (static grid: x = block chunk, y = point tile;
+// chunks entirely after the tile's last run start exit at once).
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kFwdThreads) void k_fwd_all(const uint32_t *__restrict__ tabs,
+                                                         int32_t nblk,
+                                                         const uint32_t *__restrict__ recs,
+                                                         const int32_t *__restrict__ runstart,
+                                                         int32_t N, int32_t *__restrict__ dom_in,
+                                                         const DevScalars *__restrict__ sc) {
+    constexpr int TS = blk_stride(M);
+    constexpr int CB = blocks_per_chunk<M>();
+    __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
+    if (sc->err) return;
+    const int32_t ic = blockIdx.x, jt = blockIdx.y;
+    const int32_t b0 = ic * CB;
+    if (b0 >= nblk) return;
+    const int32_t tile0 = jt * kTileJ;
+    const int32_t tile_last = min(tile0 + kTileJ - 1, N - 1);
+    if (b0 * kBlk >= runstart[tile_last]) return;  // no candidate before any run start
+    const int32_t nb = min(CB, nblk - b0);
+    stage_tables<M>(lt, tabs, b0, nb);
+    __syncthreads();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = (int)lane_id();
+    const int32_t jbase = tile0 + w * kWave * kTJ;
+    if (jbase >= N) return;
+    uint32_t kj[kTJ][M];
+    int32_t run[kTJ], cnt[kTJ];
+    load_points<M>(recs, runstart, N, jbase, lane, kj, run);
+#pragma unroll
+    for (int t = 0; t < kTJ; ++t) cnt[t] = 0;
+    const int32_t run_lo = __builtin_amdgcn_readfirstlane(runstart[jbase]);
+    const int32_t run_hi = __builtin_amdgcn_readfirstlane(runstart[min(jbase + kWave * kTJ - 1, N - 1)]);
+    fwd_blocks<M>(lt, nb, run_lo, run_hi, kj, run, cnt);
+#pragma unroll
+    for (int t = 0; t < kTJ; ++t) {
+        const int32_t q = jbase + t * kWave + lane;
+        if (q < N && cnt[t]) atomicAdd(&dom_in[q], cnt[t]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Peeling decrements of one level: blocks of the front F_k against the
+// unranked list U_k.  Sizes come from the device; work items are handed out
+// by block index first, then by a counter.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
+    const uint32_t *__restrict__ tabs, const uint32_t *__restrict__ uk,
+    const int32_t *__restrict__ urun, int32_t *__restrict__ ucnt, int32_t level,
+    const int32_t *__restrict__ fsize, const int32_t *__restrict__ usize,
+    uint32_t *__restrict__ work, const DevScalars *__restrict__ sc) {
+    constexpr int TS = blk_stride(M);
+    constexpr int CB = blocks_per_chunk<M>();
+    __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
+    __shared__ int32_t s_item;
+    if (sc->err) return;
+    const int32_t nf = fsize[level];
+    const int32_t nu = usize[level];
+    if (nf == 0 || nu == 0) return;
+    const int32_t nblk = (nf + kBlk - 1) / kBlk;
+    const int32_t nIC = (nblk + CB - 1) / CB;
+    const int32_t nJT = (nu + kTileJ - 1) / kTileJ;
+    const int64_t nitems = (int64_t)nIC * nJT;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = (int)lane_id();
+    int64_t item = blockIdx.x;
+    while (item < nitems) {
+        const int32_t ic = (int32_t)(item / nJT);
+        const int32_t jt = (int32_t)(item % nJT);
+        const int32_t b0 = ic * CB;
+        const int32_t nb = min(CB, nblk - b0);
+        const int32_t tile0 = jt * kTileJ;
+        const int32_t tile_last = min(tile0 + kTileJ - 1, nu - 1);
+        if ((int32_t)tabs[(size_t)b0 * TS] < urun[tile_last]) {  // block-uniform
+            stage_tables<M>(lt, tabs, b0, nb);
+            __syncthreads();
+            const int32_t jbase = tile0 + w * kWave * kTJ;
+            if (jbase < nu) {
+                uint32_t kj[kTJ][M];
+                int32_t run[kTJ], cnt[kTJ];
+                load_points<M>(uk, urun, nu, jbase, lane, kj, run);
+#pragma unroll
+                for (int t = 0; t < kTJ; ++t) cnt[t] = 0;
+                const int32_t run_lo = __builtin_amdgcn_readfirstlane(urun[jbase]);
+                const int32_t run_hi =
+                    __builtin_amdgcn_readfirstlane(urun[min(jbase + kWave * kTJ - 1, nu - 1)]);
+                fwd_blocks<M>(lt, nb, run_lo, run_hi, kj, run, cnt);
+#pragma unroll
+                for (int t = 0; t < kTJ; ++t) {
+                    const int32_t q = jbase + t * kWave + lane;
+                    if (q < nu && cnt[t]) atomicSub(&ucnt[q], cnt[t]);
+                }
+            }
+        }
+        if (threadIdx.x == 0) s_item = (int32_t)(gridDim.x + atomicAdd(&work[level], 1u));
+        __syncthreads();  // every wave is done with lt
+        item = s_item;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Out-degrees over all points: each lane an earlier point i, later blocks;
+// members j count when every key of j is >= i's and j lies in a later run
+// (position >= runend(i)).
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kFwdThreads) void k_bwd_all(const uint32_t *__restrict__ tabs,
+                                                         int32_t nblk,
+                                                         const uint32_t *__restrict__ recs,
+                                                         const int32_t *__restrict__ runend,
+                                                         int32_t N, int32_t *__restrict__ dom_out,
+                                                         const DevScalars *__restrict__ sc) {
+    constexpr int TS = blk_stride(M);
+    constexpr int CB = blocks_per_chunk<M>();
+    __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
+    if (sc->err) return;
+    const int32_t jc = blockIdx.x, it = blockIdx.y;
+    const int32_t b0 = jc * CB;
+    if (b0 >= nblk) return;
+    const int32_t nb = min(CB, nblk - b0);
+    const int32_t tile0 = it * kTileJ;
+    const int32_t chunk_last = min((b0 + nb) * kBlk, N) - 1;
+    if (chunk_last < runend[tile0]) return;  // every member precedes every run end
+    stage_tables<M>(lt, tabs, b0, nb);
+    __syncthreads();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = (int)lane_id();
+    const int32_t ibase = tile0 + w * kWave * kTJ;
+    if (ibase >= N) return;
+    constexpr int MP = rec_stride(M);
+    uint32_t ki[kTJ][M];
+    int32_t rend[kTJ], cnt[kTJ];
+#pragma unroll
+    for (int t = 0; t < kTJ; ++t) {
+        const int32_t q = ibase + t * kWave + lane;
+        cnt[t] = 0;
+        if (q < N) {
+#pragma unroll
+            for (int k = 0; k < M; ++k) ki[t][k] = recs[(size_t)q * MP + k];
+            rend[t] = runend[q];
+        } else {
+#pragma unroll
+            for (int k = 0; k < M; ++k) ki[t][k] = 0xffffffffu;
+            rend[t] = 0x7fffffff;  // dominates nothing
+        }
+    }
+    const int32_t rend_lo = __builtin_amdgcn_readfirstlane(runend[ibase]);
+    const int32_t rend_hi = __builtin_amdgcn_readfirstlane(runend[min(ibase + kWave * kTJ - 1, N - 1)]);
+    for (int32_t b = 0; b < nb; ++b) {
+        const uint32_t *T = lt + b * TS;
+        const int32_t bmin = (int32_t)T[0];
+        const int32_t bmax = (int32_t)T[1];
+        if (bmax < rend_lo) continue;  // the whole block precedes every run end
+        const uint64_t members = low_bits(T[2]);
+        const bool full = bmin >= rend_hi;
+#pragma unroll
+        for (int t = 0; t < kTJ; ++t) {
+            uint64_t m = members;
+            if (!full) {
+                if (rend[t] > bmax) m = 0ull;
+                else if (rend[t] > bmin)
+                    m &= ~low_bits(count_pos_lt64(reinterpret_cast<const int32_t *>(T + blk_pos_off()),
+                                                  rend[t]));
+            }
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const uint32_t c = count_lt64(T + blk_key_off(k), ki[t][k]);
+                m &= ~reinterpret_cast<const uint64_t *>(T + blk_pm_off(M, k))[c];
+            }
+            cnt[t] += __popcll(m);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kTJ; ++t) {
+        const int32_t q = ibase + t * kWave + lane;
+        if (q < N && cnt[t]) atomicAdd(&dom_out[q], cnt[t]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int M>
+static hipError_t launch_counts(const SortViews &v, hipStream_t s) {
+    const int32_t N = (int32_t)v.N;
+    const int32_t nblk = (N + kBlk - 1) / kBlk;
+    constexpr int CB = blocks_per_chunk<M>();
+    hipLaunchKernelGGL(k_build_blocks<M>, dim3((unsigned)nblk), dim3(64), 0, s, v.recs, N,
+                       (const int32_t *)nullptr, v.tabs_all, v.sc);
+    const unsigned nIC = (unsigned)((nblk + CB - 1) / CB);
+    const unsigned nJT = (unsigned)((N + kTileJ - 1) / kTileJ);
+    hipLaunchKernelGGL(k_fwd_all<M>, dim3(nIC, nJT), dim3(kFwdThreads), 0, s, v.tabs_all, nblk,
+                       v.recs, v.runstart, N, v.dom_in_s, v.sc);
+    if (v.dom_out)
+        hipLaunchKernelGGL(k_bwd_all<M>, dim3(nIC, nJT), dim3(kFwdThreads), 0, s, v.tabs_all, nblk,
+                           v.recs, v.runend, N, v.dom_out_s, v.sc);
+    return hipGetLastError();
+}
+
+hipError_t run_bit_counts(const SortViews &v, hipStream_t s) {
+    switch (v.M) {
+#define NSGA3_CASE(m) case m: return launch_counts<m>(v, s);
+        NSGA3_CASE(2) NSGA3_CASE(3) NSGA3_CASE(4) NSGA3_CASE(5) NSGA3_CASE(6) NSGA3_CASE(7)
+        NSGA3_CASE(8) NSGA3_CASE(9) NSGA3_CASE(10) NSGA3_CASE(11) NSGA3_CASE(12) NSGA3_CASE(13)
+        NSGA3_CASE(14) NSGA3_CASE(15) NSGA3_CASE(16)
+#undef NSGA3_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int M>
+static void launch_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk,
+                         const int32_t *urun, int32_t *ucnt, int level, unsigned grid, hipStream_t s) {
+    const int32_t N = (int32_t)v.N;
+    const int32_t nblk_max = (N + kBlk - 1) / kBlk;
+    hipLaunchKernelGGL(k_build_blocks<M>, dim3((unsigned)nblk_max), dim3(64), 0, s, fk, -1,
+                       v.fsize + level, v.tabs_lvl, v.sc);
+    hipLaunchKernelGGL(k_fwd_level<M>, dim3(grid), dim3(kFwdThreads), 0, s, v.tabs_lvl, uk, urun,
+                       ucnt, level, v.fsize, v.usize, v.work, v.sc);
+}
+
+void run_bit_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk, const int32_t *urun,
+                   int32_t *ucnt, int level, unsigned grid, hipStream_t s) {
+    switch (v.M) {
+#define NSGA3_CASE(m) case m: launch_level<m>(v, fk, uk, urun, ucnt, level, grid, s); break;
+        NSGA3_CASE(2) NSGA3_CASE(3) NSGA3_CASE(4) NSGA3_CASE(5) NSGA3_CASE(6) NSGA3_CASE(7)
+        NSGA3_CASE(8) NSGA3_CASE(9) NSGA3_CASE(10) NSGA3_CASE(11) NSGA3_CASE(12) NSGA3_CASE(13)
+        NSGA3_CASE(14) NSGA3_CASE(15) NSGA3_CASE(16)
+#undef NSGA3_CASE
+        default: break;
+    }
+}
+
+size_t bit_tables_bytes(int64_t N, int M) {
+    return (size_t)((N + kBlk - 1) / kBlk) * (size_t)blk_stride(M) * sizeof(uint32_t);
+}
+
+}  // namespace nsga3

@@ -72,6 +72,7 @@ __global__ __launch_bounds__(kThreads) void k_build_recs(const float *__restrict
                                                          const uint32_t *__restrict__ sval,
                                                          uint32_t *__restrict__ recs,
                                                          int32_t *__restrict__ runstart,
+                                                         int32_t *__restrict__ runend,
                                                          const DevScalars *__restrict__ sc) {
     if (sc->err) return;
     const int MP = rec_stride(M);
@@ -91,6 +92,13 @@ __global__ __launch_bounds__(kThreads) void k_build_recs(const float *__restrict
         if (skey[mid] < me) lo = mid + 1; else hi = mid;
     }
     runstart[p] = (int32_t)lo;
+    lo = p + 1;  // first q > p with a larger key sum
+    hi = N;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (skey[mid] <= me) lo = mid + 1; else hi = mid;
+    }
+    runend[p] = (int32_t)lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -188,8 +196,13 @@ static hipError_t launch_counts_and_peel(const SortViews &v, const uint32_t *sva
     const int64_t nJT = (N + kJT - 1) / kJT;
     const int64_t items = nJT * (nJT + 1) / 2;
     v.mark();
-    hipLaunchKernelGGL(k_domcount<M>, dim3((unsigned)items), dim3(kThreads), 0, s, v.recs,
-                       v.runstart, (int32_t)N, v.dom_in_s, v.dom_out_s, v.sc);
+    if (cfg.bitsets) {
+        hipError_t e = run_bit_counts(v, s);
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(k_domcount<M>, dim3((unsigned)items), dim3(kThreads), 0, s, v.recs,
+                           v.runstart, (int32_t)N, v.dom_in_s, v.dom_out_s, v.sc);
+    }
     v.mark();
     hipError_t e = run_peel(v, cfg, s);
     if (e != hipSuccess) return e;
@@ -210,7 +223,7 @@ hipError_t run_sort_stage(const SortViews &v, const LaunchCfg &cfg, hipStream_t 
     const uint64_t *skey = in_alt ? v.skey_alt : v.skey;
     const uint32_t *sval = in_alt ? v.sval_alt : v.sval;
     hipLaunchKernelGGL(k_build_recs, dim3(nbN), dim3(kThreads), 0, s, v.objs, N, v.M, skey, sval,
-                       v.recs, v.runstart, v.sc);
+                       v.recs, v.runstart, v.runend, v.sc);
     switch (v.M) {
 #define NSGA3_CASE(m) case m: return launch_counts_and_peel<m>(v, sval, cfg, s);
         NSGA3_CASE(2) NSGA3_CASE(3) NSGA3_CASE(4) NSGA3_CASE(5) NSGA3_CASE(6) NSGA3_CASE(7)

@@ -35,6 +35,9 @@ struct SortViews {
     uint32_t *temp;              // radix-sort / scan scratch
     uint32_t *recs;              // [N * rec_stride(M)] sorted records
     int32_t *runstart;           // [N]
+    int32_t *runend;             // [N] first position of the next key-sum run
+    uint32_t *tabs_all;          // block tables over all sorted points
+    uint32_t *tabs_lvl;          // block tables of the current front
     int32_t *dom_in_s, *dom_out_s, *rank_s;  // [N] in sorted order
     uint32_t *fk[2], *uk[2];     // peeling lists (records)
     int32_t *urun[2], *ucnt[2];  // peeling lists (run starts, remaining in-degree)
@@ -57,9 +60,17 @@ struct LaunchCfg {
     int peel_blocks_per_cu;     // cooperative tail kernel
     int phase_a_blocks_per_cu;  // per-level pairwise kernel
     int host_levels;            // peeling levels enqueued as ordinary launches
+    bool bitsets;               // block-bitset pair kernels (else pairwise compares)
+    bool tail_block;            // single-workgroup peeling tail (graph capture)
 };
 
 hipError_t run_sort_stage(const SortViews &v, const LaunchCfg &cfg, hipStream_t s);
+
+// ---- bitdom.hip -----------------------------------------------------------
+hipError_t run_bit_counts(const SortViews &v, hipStream_t s);
+void run_bit_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk, const int32_t *urun,
+                   int32_t *ucnt, int level, unsigned grid, hipStream_t s);
+size_t bit_tables_bytes(int64_t N, int M);
 
 // ---- peel.hip -------------------------------------------------------------
 hipError_t run_peel(const SortViews &v, const LaunchCfg &cfg, hipStream_t s);
@@ -81,6 +92,7 @@ struct SelectViews {
     double *dist64;              // [N]
     double *rhat64;              // [H*M]
     float *rhat32;               // [H*M]
+    uint16_t *rhat16;            // [Hpad*KP] bfloat16 (matrix-core screening)
     double *p_asf;               // [nb * M]
     int32_t *p_idx;              // [nb * M]
     double *p_nad;               // [nb * M]
@@ -97,8 +109,8 @@ struct SelectViews {
 };
 
 int normalize_partial_blocks(int64_t N);
-hipError_t run_refs(const float *refs, int H, int M, double *rhat64, float *rhat32, DevScalars *sc,
-                    hipStream_t s);
+hipError_t run_refs(const float *refs, int H, int M, double *rhat64, float *rhat32,
+                    uint16_t *rhat16, DevScalars *sc, hipStream_t s);
 hipError_t run_select_stage(const SelectViews &v, hipStream_t s);
 hipError_t run_init(DevScalars *sc, int32_t *zero_i32[], const int64_t zero_n[], int nzero,
                     hipStream_t s);

@@ -319,7 +319,8 @@ __device__ bool tail_split(const uint32_t *__restrict__ srec, const int32_t *__r
 template <int M>
 __device__ void tail_phase_a(const uint32_t *__restrict__ fk, int32_t nf,
                              const uint32_t *__restrict__ uk, const int32_t *__restrict__ urun,
-                             int32_t *__restrict__ ucnt, int32_t nu, uint32_t *lrec) {
+                             int32_t *__restrict__ ucnt, int32_t nu, uint32_t *lrec,
+                             int64_t item0, int64_t istride) {
     constexpr int MP = rec_stride(M);
     constexpr int IC = 8192 / MP;  // 32 KiB of records in LDS
     const int nIC = (nf + IC - 1) / IC;
@@ -327,7 +328,7 @@ __device__ void tail_phase_a(const uint32_t *__restrict__ fk, int32_t nf,
     const int64_t nitems = (int64_t)nIC * nJT;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = (int)lane_id();
-    for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+    for (int64_t item = item0; item < nitems; item += istride) {
         const int jt = (int)(item % nJT);
         const int ic = (int)(item / nJT);
         const int f0 = ic * IC;
@@ -408,9 +409,77 @@ __global__ __launch_bounds__(kThreads) void k_peel_tail(
             if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&sc->err, (uint32_t)kErrInternal);
             return;
         }
-        tail_phase_a<M>(fd, nf2, ud, rd, cd, nu2, lrec);
+        tail_phase_a<M>(fd, nf2, ud, rd, cd, nu2, lrec, blockIdx.x, gridDim.x);
         if (!grid_barrier2(bar, &sc->err)) return;
         nu = nu2;
+        ++level;
+    }
+}
+
+// Single-workgroup tail (usable inside captured graphs, where cooperative
+// launches are not): one block finishes the levels from k0 on, with block
+// barriers only.  Meant for the few points left after the enqueued levels.
+template <int M>
+__global__ __launch_bounds__(kThreads) void k_peel_tail_block(
+    int32_t k0, uint32_t *__restrict__ fk0, uint32_t *__restrict__ fk1, uint32_t *__restrict__ uk0,
+    uint32_t *__restrict__ uk1, int32_t *__restrict__ urun0, int32_t *__restrict__ urun1,
+    int32_t *__restrict__ ucnt0, int32_t *__restrict__ ucnt1, int32_t *__restrict__ rank_s,
+    int32_t *__restrict__ fsize, int32_t *__restrict__ usize, DevScalars *__restrict__ sc) {
+    constexpr int MP = rec_stride(M);
+    __shared__ __attribute__((aligned(16))) uint32_t lrec[8192];
+    __shared__ uint32_t lds[17];
+    if (sc->err) return;
+    int32_t level = k0;
+    int32_t nu = usize[level - 1];
+    if (nu == 0) return;
+    if (fsize[level - 1] == 0) {
+        if (threadIdx.x == 0) atomicOr(&sc->err, (uint32_t)kErrInternal);
+        return;
+    }
+    for (;;) {
+        const int p = (level - 1) & 1, q = level & 1;
+        const uint32_t *us = p ? uk1 : uk0;
+        const int32_t *rs = p ? urun1 : urun0;
+        const int32_t *cs = p ? ucnt1 : ucnt0;
+        uint32_t *fd = q ? fk1 : fk0;
+        uint32_t *ud = q ? uk1 : uk0;
+        int32_t *rd = q ? urun1 : urun0;
+        int32_t *cd = q ? ucnt1 : ucnt0;
+        // ordered split of U_{level-1}
+        uint32_t of = 0, ou = 0;
+        for (int32_t base = 0; base < nu; base += kThreads) {
+            const int32_t e = base + (int32_t)threadIdx.x;
+            const bool valid = e < nu;
+            const int32_t cnt = valid ? cs[e] : 1;
+            const uint32_t isf = (valid && cnt == 0) ? 1u : 0u;
+            const uint32_t isu = (valid && cnt != 0) ? 1u : 0u;
+            uint32_t totf, totu;
+            const uint32_t exf = block_exclusive_scan(isf, lds, &totf);
+            const uint32_t exu = block_exclusive_scan(isu, lds, &totu);
+            if (valid) {
+                const uint32_t *r = us + (size_t)e * MP;
+                if (isf) {
+                    copy_rec<MP>(fd + (size_t)(of + exf) * MP, r);
+                    rank_s[r[M]] = level;
+                } else {
+                    copy_rec<MP>(ud + (size_t)(ou + exu) * MP, r);
+                    rd[ou + exu] = rs[e];
+                    cd[ou + exu] = cnt;
+                }
+            }
+            of += totf;
+            ou += totu;
+        }
+        if (threadIdx.x == 0) { fsize[level] = (int32_t)of; usize[level] = (int32_t)ou; }
+        __syncthreads();
+        if (ou == 0) return;
+        if (of == 0) {
+            if (threadIdx.x == 0) atomicOr(&sc->err, (uint32_t)kErrInternal);
+            return;
+        }
+        tail_phase_a<M>(fd, (int32_t)of, ud, rd, cd, (int32_t)ou, lrec, 0, 1);
+        __syncthreads();
+        nu = (int32_t)ou;
         ++level;
     }
 }
@@ -457,8 +526,11 @@ static hipError_t launch_peel(const SortViews &v, const LaunchCfg &cfg, hipStrea
                                v.ucnt[p], -1, k, v.fk[q], v.uk[q], v.urun[q], v.ucnt[q], v.rank_s,
                                v.fsize, v.usize, lb_cur, lb_next, v.sc);
         }
-        hipLaunchKernelGGL(k_phase_a<M>, dim3(ga), dim3(kThreads), 0, s, v.fk[q], v.uk[q],
-                           v.urun[q], v.ucnt[q], k, v.fsize, v.usize, v.work, v.sc);
+        if (cfg.bitsets)
+            run_bit_level(v, v.fk[q], v.uk[q], v.urun[q], v.ucnt[q], k, ga, s);
+        else
+            hipLaunchKernelGGL(k_phase_a<M>, dim3(ga), dim3(kThreads), 0, s, v.fk[q], v.uk[q],
+                               v.urun[q], v.ucnt[q], k, v.fsize, v.usize, v.work, v.sc);
     }
     int32_t k0 = levels;
     uint32_t *fk0 = v.fk[0], *fk1 = v.fk[1], *uk0 = v.uk[0], *uk1 = v.uk[1];
@@ -469,10 +541,15 @@ static hipError_t launch_peel(const SortViews &v, const LaunchCfg &cfg, hipStrea
     GridBar *bar = v.bar;
     void *args[] = {&k0, &fk0, &fk1, &uk0, &uk1, &urun0, &urun1, &ucnt0, &ucnt1, &rank_s,
                     &fsize, &usize, &blkcnt, &sc, &bar};
-    const int grid = cfg.num_cus * cfg.peel_blocks_per_cu;
-    hipError_t e = hipLaunchCooperativeKernel((const void *)k_peel_tail<M>, dim3(grid),
-                                              dim3(kThreads), args, 0, s);
-    if (e != hipSuccess) return e;
+    if (cfg.tail_block) {
+        hipLaunchKernelGGL(k_peel_tail_block<M>, dim3(1), dim3(kThreads), 0, s, k0, fk0, fk1, uk0,
+                           uk1, urun0, urun1, ucnt0, ucnt1, rank_s, fsize, usize, sc);
+    } else {
+        const int grid = cfg.num_cus * cfg.peel_blocks_per_cu;
+        hipError_t e = hipLaunchCooperativeKernel((const void *)k_peel_tail<M>, dim3(grid),
+                                                  dim3(kThreads), args, 0, s);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_last_front, dim3(1), dim3(64), 0, s, v.fsize, v.usize, v.N, v.K, v.sc);
     return hipGetLastError();
 }

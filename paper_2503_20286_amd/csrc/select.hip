@@ -28,7 +28,7 @@
 namespace nsga3 {
 
 constexpr int kNormThreads = 256;
-constexpr int kNormBlocksMax = 1024;
+constexpr int kNormBlocksMax = 256;
 
 // ---------------------------------------------------------------------------
 // init: clear per-call scalars and counters (fill kernels, no memset nodes)
@@ -77,9 +77,21 @@ hipError_t run_init(DevScalars *sc, int32_t *zero_i32[], const int64_t zero_n[],
 // ---------------------------------------------------------------------------
 // reference directions: validity and unit vectors (float64 and float32)
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);  // finite inputs only
+}
+
+// Unit reference directions in float64 and float32, and in bfloat16 for the
+// matrix-core screening: [Hpad x KP] (KP = 8 for M <= 8, else 16), rows and
+// columns beyond (H, M) zero.
 __global__ void k_refs(const float *__restrict__ refs, int H, int M, double *__restrict__ rhat64,
-                       float *__restrict__ rhat32, DevScalars *__restrict__ sc) {
+                       float *__restrict__ rhat32, uint16_t *__restrict__ rhat16, int Hpad, int KP,
+                       DevScalars *__restrict__ sc) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < Hpad && rhat16) {
+        for (int k = 0; k < KP; ++k) rhat16[(int64_t)j * KP + k] = 0;
+    }
     if (j >= H) return;
     double nn = 0.0;
     bool bad = false;
@@ -99,6 +111,7 @@ __global__ void k_refs(const float *__restrict__ refs, int H, int M, double *__r
         const double r = (double)refs[(int64_t)j * M + k] / n;
         rhat64[(int64_t)j * M + k] = r;
         rhat32[(int64_t)j * M + k] = (float)r;
+        if (rhat16) rhat16[(int64_t)j * KP + k] = bf16_rne((float)r);
     }
 }
 
@@ -279,15 +292,27 @@ __global__ __launch_bounds__(64) void k_solve(const float *__restrict__ objs, in
 }
 
 // ---------------------------------------------------------------------------
-// a6/a7: association (float32 screening, float64 re-scoring) and counts
+// a6/a7: association (float32 screening, float64 re-scoring) and counts.
+// The float32 unit references are staged in LDS when they fit (the loop over
+// references is uniform, so every read is a broadcast).
 // ---------------------------------------------------------------------------
+constexpr int kAssocLdsFloats = 8192;
+
+template <int M>
 __global__ __launch_bounds__(kNormThreads) void k_associate(
-    const float *__restrict__ objs, int64_t N, int M, const int32_t *__restrict__ rank,
+    const float *__restrict__ objs, int64_t N, const int32_t *__restrict__ rank,
     const double *__restrict__ rhat64, const float *__restrict__ rhat32, int H,
     int32_t *__restrict__ niche, float *__restrict__ dist, double *__restrict__ dist64,
     int32_t *__restrict__ rho, int32_t *__restrict__ bcount, uint8_t *__restrict__ selflag,
     DevScalars *__restrict__ sc) {
+    __shared__ float lr[kAssocLdsFloats];
     if (sc->err) return;
+    const bool in_lds = H * M <= kAssocLdsFloats;
+    if (in_lds) {
+        for (int q = threadIdx.x; q < H * M; q += kNormThreads) lr[q] = rhat32[q];
+        __syncthreads();
+    }
+    const float *R = in_lds ? lr : rhat32;
     const int32_t l = sc->last_front;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
@@ -299,31 +324,26 @@ __global__ __launch_bounds__(kNormThreads) void k_associate(
         selflag[i] = 0;
         return;
     }
-    double fp[16];
-    float y[16];
+    double fp[M];
+    float y[M];
     double mx = 0.0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        fp[k] = 0.0;
-        if (k < M) {
-            fp[k] = ((double)objs[i * M + k] - sc->z[k]) / sc->a[k];
-            mx = fp[k] > mx ? fp[k] : mx;
-        }
+    for (int k = 0; k < M; ++k) {
+        fp[k] = ((double)objs[i * M + k] - sc->z[k]) / sc->a[k];
+        mx = fp[k] > mx ? fp[k] : mx;
     }
     float l1 = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        y[k] = (k < M && mx > 0.0) ? (float)(fp[k] / mx) : 0.0f;
+    for (int k = 0; k < M; ++k) {
+        y[k] = mx > 0.0 ? (float)(fp[k] / mx) : 0.0f;
         l1 += y[k];
     }
-    // screening: s_j = y . rhat_j in float32 (scale of y does not move argmax)
+    // screening: s_j = y . rhat_j in float32 (the scale of y does not move argmax)
     float smax = -FLT_MAX;
     for (int j = 0; j < H; ++j) {
-        const float *rr = rhat32 + (int64_t)j * M;
         float s = 0.0f;
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-            if (k < M) s = __fmaf_rn(y[k], rr[k], s);
+        for (int k = 0; k < M; ++k) s = __fmaf_rn(y[k], R[j * M + k], s);
         smax = s > smax ? s : smax;
     }
     // |s32 - s| <= (M + 3) u ||y||_2 <= (M + 3) u ||y||_1 with u = 2^-24; keep a
@@ -333,16 +353,16 @@ __global__ __launch_bounds__(kNormThreads) void k_associate(
     double d1 = DBL_MAX, d2 = DBL_MAX;
     int32_t best = 0;
     for (int j = 0; j < H; ++j) {
-        const float *rr = rhat32 + (int64_t)j * M;
         float s = 0.0f;
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-            if (k < M) s = __fmaf_rn(y[k], rr[k], s);
+        for (int k = 0; k < M; ++k) s = __fmaf_rn(y[k], R[j * M + k], s);
         if (s < thr) continue;
         const double *rd = rhat64 + (int64_t)j * M;
         double s64 = 0.0;
+#pragma unroll
         for (int k = 0; k < M; ++k) s64 = s64 + fp[k] * rd[k];
         double q = 0.0;
+#pragma unroll
         for (int k = 0; k < M; ++k) {
             const double e = fp[k] - s64 * rd[k];
             q = q + e * e;
@@ -350,6 +370,160 @@ __global__ __launch_bounds__(kNormThreads) void k_associate(
         const double d = sqrt(q);
         if (d < d1) { d2 = d1; d1 = d; best = j; }
         else if (d < d2) { d2 = d; }
+    }
+    niche[i] = best;
+    if (dist) dist[i] = (float)d1;
+    dist64[i] = d1;
+    if (d2 != DBL_MAX && (d2 - d1) < 1e-6 * fmax(d2, 1e-300)) atomicAdd(&sc->near_ties, 1);
+    if (r < l) {
+        atomicAdd(&rho[best], 1);
+        selflag[i] = 1;
+    } else {
+        atomicAdd(&bcount[best], 1);
+        selflag[i] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a6/a7, matrix-core form: the screening dot products s = y . rhat are one
+// bfloat16 MFMA per 32 references x 32 points (float32 accumulate); refs are
+// the A operand (rows), points the B operand (columns), so each lane holds one
+// point (column l % 32) and 16 of the 32 references of the tile.  The band
+// covers the bfloat16 rounding of both operands; survivors are re-scored in
+// float64 exactly as in the float32 form.
+// ---------------------------------------------------------------------------
+typedef float mfma_f16v __attribute__((ext_vector_type(16)));
+typedef short mfma_s4v __attribute__((ext_vector_type(4)));
+typedef __bf16 mfma_b8v __attribute__((ext_vector_type(8)));
+
+template <int KP>
+struct BfOperand;
+template <>
+struct BfOperand<8> {
+    using T = mfma_s4v;  // 4 bf16 per lane (k = 4 * (lane / 32) + v)
+    static __device__ __forceinline__ mfma_f16v mma(T a, T b, mfma_f16v c) {
+        return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ void set(T &x, int v, uint16_t bits) { x[v] = (short)bits; }
+    static constexpr int kPerLane = 4;
+};
+template <>
+struct BfOperand<16> {
+    using T = mfma_b8v;  // 8 bf16 per lane (k = 8 * (lane / 32) + v)
+    static __device__ __forceinline__ mfma_f16v mma(T a, T b, mfma_f16v c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ void set(T &x, int v, uint16_t bits) {
+        x[v] = __builtin_bit_cast(__bf16, bits);
+    }
+    static constexpr int kPerLane = 8;
+};
+
+template <int M>
+__global__ __launch_bounds__(256) void k_associate_bf16(
+    const float *__restrict__ objs, int64_t N, const int32_t *__restrict__ rank,
+    const double *__restrict__ rhat64, const uint16_t *__restrict__ rhat16, int H,
+    int32_t *__restrict__ niche, float *__restrict__ dist, double *__restrict__ dist64,
+    int32_t *__restrict__ rho, int32_t *__restrict__ bcount, uint8_t *__restrict__ selflag,
+    DevScalars *__restrict__ sc) {
+    constexpr int KP = M <= 8 ? 8 : 16;
+    using Op = BfOperand<KP>;
+    constexpr int KL = Op::kPerLane;
+    if (sc->err) return;
+    const int32_t l = sc->last_front;
+    const int lane = (int)lane_id();
+    const int half = lane >> 5;                       // which k-slice / row half this lane holds
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t i = wave * 32 + (lane & 31);        // this lane's point (shared with lane ^ 32)
+    const bool inrange = i < N;
+    const int32_t r = inrange ? rank[i] : 0x7fffffff;
+    const bool active = inrange && r <= l;
+    double fp[M];
+    double mx = 0.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        fp[k] = active ? ((double)objs[i * M + k] - sc->z[k]) / sc->a[k] : 0.0;
+        mx = fp[k] > mx ? fp[k] : mx;
+    }
+    float y[M];
+    float n2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        y[k] = mx > 0.0 ? (float)(fp[k] / mx) : 0.0f;
+        n2 = __fmaf_rn(y[k], y[k], n2);
+    }
+    // B operand: this lane's point, k-slice [KL * half, KL * half + KL)
+    typename Op::T bop;
+#pragma unroll
+    for (int v = 0; v < KL; ++v) {
+        const int k = KL * half + v;
+        float val = 0.0f;
+#pragma unroll
+        for (int q = 0; q < M; ++q)
+            if (q == k) val = y[q];
+        Op::set(bop, v, bf16_rne(val));
+    }
+    const int ntiles = (H + 31) / 32;
+    float smax = -FLT_MAX;
+    for (int tl = 0; tl < ntiles; ++tl) {
+        const typename Op::T aop = *reinterpret_cast<const typename Op::T *>(
+            rhat16 + ((int64_t)(tl * 32 + (lane & 31)) * KP + KL * half));
+        mfma_f16v acc = {};
+        acc = Op::mma(aop, bop, acc);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int j = tl * 32 + 8 * (v / 4) + 4 * half + (v % 4);
+            if (j < H) smax = acc[v] > smax ? acc[v] : smax;
+        }
+    }
+    smax = fmaxf(smax, __shfl_xor(smax, 32, 64));
+    // |s_bf16 - s| <= (2 u + u^2) ||y||_2 + float32 rounding, u = 2^-8; doubled
+    const float band = 2.0f * 1.01f * (0.0078125f + 0.000244f) * sqrtf(n2) + 1e-30f;
+    const float thr = smax - band;
+    double d1 = DBL_MAX, d2 = DBL_MAX;
+    int32_t best = 0x7fffffff;
+    for (int tl = 0; tl < ntiles; ++tl) {
+        const typename Op::T aop = *reinterpret_cast<const typename Op::T *>(
+            rhat16 + ((int64_t)(tl * 32 + (lane & 31)) * KP + KL * half));
+        mfma_f16v acc = {};
+        acc = Op::mma(aop, bop, acc);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int j = tl * 32 + 8 * (v / 4) + 4 * half + (v % 4);
+            if (j >= H || acc[v] < thr || !active) continue;
+            const double *rd = rhat64 + (int64_t)j * M;
+            double s64 = 0.0;
+#pragma unroll
+            for (int k = 0; k < M; ++k) s64 = s64 + fp[k] * rd[k];
+            double q = 0.0;
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const double e = fp[k] - s64 * rd[k];
+                q = q + e * e;
+            }
+            const double d = sqrt(q);
+            if (d < d1 || (d == d1 && j < best)) { d2 = d1; d1 = d; best = j; }
+            else if (d < d2 || d == d2) { d2 = d < d2 ? d : d2; }
+        }
+    }
+    // merge with the lane holding the other 16 references of every tile
+    const double od1 = __shfl_xor(d1, 32, 64);
+    const double od2 = __shfl_xor(d2, 32, 64);
+    const int32_t obest = __shfl_xor(best, 32, 64);
+    if (od1 < d1 || (od1 == d1 && obest < best)) {
+        d2 = fmin(d1, od2);
+        d1 = od1;
+        best = obest;
+    } else {
+        d2 = fmin(d2, od1);
+    }
+    if (!inrange || half != 0) return;
+    if (!active) {
+        niche[i] = -1;
+        if (dist) dist[i] = -1.0f;
+        dist64[i] = -1.0;
+        selflag[i] = 0;
+        return;
     }
     niche[i] = best;
     if (dist) dist[i] = (float)d1;
@@ -497,6 +671,7 @@ __global__ __launch_bounds__(256) void k_bucket_rank(int64_t nl, const int32_t *
     const int32_t j = niche[i];
     const int32_t b0 = bstart[j], b1 = bstart[j + 1];
     int32_t t = 0;
+#pragma unroll 8
     for (int32_t m = b0; m < b1; ++m) {
         const double dm = bd[m];
         const int32_t im = bi[m];
@@ -543,9 +718,25 @@ hipError_t run_select_stage(const SelectViews &v, hipStream_t s) {
                        v.p_nad, v.sc);
     const unsigned nbN = (unsigned)((N + 255) / 256);
     v.mark();
-    hipLaunchKernelGGL(k_associate, dim3(nbN), dim3(kNormThreads), 0, s, v.objs, N, M, v.rank,
-                       v.rhat64, v.rhat32, v.H, v.niche, v.dist, v.dist64, v.rho, v.bcount,
-                       v.selflag, v.sc);
+    const unsigned nbW = (unsigned)((N + 127) / 128);  // 32 points per wave, 4 waves per block
+    switch (M) {
+#define NSGA3_CASE(m)                                                                               \
+    case m:                                                                                         \
+        if (v.assoc_mode == NSGA3_ASSOC_BF16)                                                       \
+            hipLaunchKernelGGL(k_associate_bf16<m>, dim3(nbW), dim3(256), 0, s, v.objs, N, v.rank,  \
+                               v.rhat64, v.rhat16, v.H, v.niche, v.dist, v.dist64, v.rho,           \
+                               v.bcount, v.selflag, v.sc);                                          \
+        else                                                                                        \
+            hipLaunchKernelGGL(k_associate<m>, dim3(nbN), dim3(kNormThreads), 0, s, v.objs, N,      \
+                               v.rank, v.rhat64, v.rhat32, v.H, v.niche, v.dist, v.dist64, v.rho,   \
+                               v.bcount, v.selflag, v.sc);                                          \
+        break;
+        NSGA3_CASE(2) NSGA3_CASE(3) NSGA3_CASE(4) NSGA3_CASE(5) NSGA3_CASE(6) NSGA3_CASE(7)
+        NSGA3_CASE(8) NSGA3_CASE(9) NSGA3_CASE(10) NSGA3_CASE(11) NSGA3_CASE(12) NSGA3_CASE(13)
+        NSGA3_CASE(14) NSGA3_CASE(15) NSGA3_CASE(16)
+#undef NSGA3_CASE
+        default: return hipErrorInvalidValue;
+    }
     v.mark();
     hipLaunchKernelGGL(k_niche_plan, dim3(1), dim3(1024), 0, s, v.H, v.rho, v.bcount, v.bstart,
                        v.bcursor, v.sc);
@@ -559,9 +750,12 @@ hipError_t run_select_stage(const SelectViews &v, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t run_refs(const float *refs, int H, int M, double *rhat64, float *rhat32, DevScalars *sc,
-                    hipStream_t s) {
-    hipLaunchKernelGGL(k_refs, dim3((H + 255) / 256), dim3(256), 0, s, refs, H, M, rhat64, rhat32, sc);
+hipError_t run_refs(const float *refs, int H, int M, double *rhat64, float *rhat32,
+                    uint16_t *rhat16, DevScalars *sc, hipStream_t s) {
+    const int Hpad = (H + 31) / 32 * 32;
+    const int KP = M <= 8 ? 8 : 16;
+    hipLaunchKernelGGL(k_refs, dim3((Hpad + 255) / 256), dim3(256), 0, s, refs, H, M, rhat64,
+                       rhat32, rhat16, Hpad, KP, sc);
     return hipGetLastError();
 }
 

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *__restri
         if (p < n) atomicAdd(&h[(uint32_t)(keys[p] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    hist[(size_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];  // block-major
 }
 
 // Exclusive scan of `n` uint32 values in place, one block of 1024 threads.
@@ -64,26 +64,30 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *__res
     // Offsets of this block's digits: all keys with a smaller digit, plus keys
     // with the same digit in earlier blocks.  The histogram (digit-major) is
     // read cooperatively and summed with LDS atomics.
-    base_off[tid] = 0;
-    run[tid] = 0;
-    __syncthreads();
-    const int64_t nh = (int64_t)256 * nblocks;
-    for (int64_t x = tid; x < nh; x += kRsThreads) {
-        const uint32_t d = (uint32_t)(x / nblocks);
-        const uint32_t b = (uint32_t)(x - (int64_t)d * nblocks);
-        const uint32_t h = offs[x];
-        if (h) {
-            atomicAdd(&run[d], h);                      // digit total
-            if (b < blockIdx.x) atomicAdd(&base_off[d], h);  // same digit, earlier blocks
-        }
-    }
-    __syncthreads();
     {
+        // thread = digit: sum the digit's counts over all blocks and over the
+        // blocks before this one (block-major histogram: coalesced rows)
+        uint32_t before = 0, total = 0;
+        int b = 0;
+        for (; b + 4 <= nblocks; b += 4) {
+            const uint32_t h0 = offs[(size_t)(b + 0) * 256 + tid];
+            const uint32_t h1 = offs[(size_t)(b + 1) * 256 + tid];
+            const uint32_t h2 = offs[(size_t)(b + 2) * 256 + tid];
+            const uint32_t h3 = offs[(size_t)(b + 3) * 256 + tid];
+            total += h0 + h1 + h2 + h3;
+            before += (b + 0 < (int)blockIdx.x ? h0 : 0u) + (b + 1 < (int)blockIdx.x ? h1 : 0u) +
+                      (b + 2 < (int)blockIdx.x ? h2 : 0u) + (b + 3 < (int)blockIdx.x ? h3 : 0u);
+        }
+        for (; b < nblocks; ++b) {
+            const uint32_t h = offs[(size_t)b * 256 + tid];
+            total += h;
+            before += b < (int)blockIdx.x ? h : 0u;
+        }
         uint32_t tot;
-        const uint32_t ex = block_exclusive_scan(run[tid], scan_lds, &tot);
-        base_off[tid] += ex;
+        const uint32_t ex = block_exclusive_scan(total, scan_lds, &tot);
+        base_off[tid] = ex + before;
+        run[tid] = 0;
     }
-    run[tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRsTile;
     for (int it = 0; it < kRsItems; ++it) {

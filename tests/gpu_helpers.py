@@ -9,6 +9,7 @@ import oracle
 def gpu_select(objs: np.ndarray, refs: np.ndarray, K: int, **kw):
     import torch
     import paper_2503_20286_amd as nsga3
+    # pass assoc=... (and any other select() keyword) straight through
     o = torch.from_numpy(np.ascontiguousarray(objs, np.float32)).cuda()
     r = torch.from_numpy(np.ascontiguousarray(refs, np.float32)).cuda()
     res = nsga3.select(o, r, K, **kw)

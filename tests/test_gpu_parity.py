@@ -227,3 +227,81 @@ def test_many_objectives_full_size_sampled():
     w = workloads.make("many")
     print(f"many N={w.N}", flush=True)
     _check_large_scale(w, n_samples=24)
+
+
+# ---------------------------------------------------------------------------
+# Matrix-core (bfloat16) screening of the association: same contract.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,N", [("small", None), ("ties", 3000), ("large", 5000), ("many", 4000)])
+def test_bf16_association_parity(name, N):
+    import paper_2503_20286_amd as nsga3
+    w = workloads.make(name, N=N)
+    print(f"bf16 case {name} N={w.N} M={w.M} H={w.H}", flush=True)
+    g = gpu_select(w.objs, w.refs, w.K, assoc=nsga3.ASSOC_BF16)
+    _zero(compare_full(w.objs, w.refs, w.K, g))
+
+
+@pytest.mark.parametrize("M", [2, 7, 8, 9, 16])
+def test_bf16_objective_counts(M):
+    import paper_2503_20286_amd as nsga3
+    rng = np.random.default_rng(100 + M)
+    F = workloads.sphere_shell(rng, 1200, M, lambda g, n: g.uniform(0, 0.4, n), 0.2).astype(np.float32)
+    p = {2: 40, 7: 2, 8: 2, 9: 2, 16: 1}[M]
+    R = workloads.das_dennis(M, p).astype(np.float32)
+    g = gpu_select(F, R, 600, assoc=nsga3.ASSOC_BF16)
+    _zero(compare_full(F, R, 600, g))
+
+
+def test_bf16_many_full_size_sampled():
+    import paper_2503_20286_amd as nsga3
+    w = workloads.make("many")
+    print(f"bf16 many N={w.N}", flush=True)
+    g = gpu_select(w.objs, w.refs, w.K, assoc=nsga3.ASSOC_BF16)
+    ref = gpu_select(w.objs, w.refs, w.K)
+    # same ranks from both modes; association must agree with float64 outside ties
+    assert np.array_equal(g["rank"], ref["rank"])
+    rank = g["rank"]
+    l = g["info"].last_front
+    nz = oracle.normalize(w.objs, rank, l)
+    niche, dist, gap = oracle.associate(w.objs, rank, l, nz.z, nz.a, w.refs)
+    S = rank <= l
+    tie = S & (gap < 1e-6)
+    assert int(np.sum((g["niche"] != niche) & ~tie)) == 0
+    assert np.array_equal(g["selected"], ref["selected"]) or np.any(tie)
+
+
+@pytest.mark.parametrize("name,N", [("ties", 3000), ("large", 5000), ("many", 3000)])
+def test_pairwise_compare_path_parity(name, N, monkeypatch):
+    """The pairwise-compare dominance kernels (kept beside the block-bitset
+    ones) must give the same results."""
+    import paper_2503_20286_amd as nsga3
+    monkeypatch.setenv("NSGA3_PAIRWISE", "1")
+    ctx = nsga3.Context(0)
+    monkeypatch.delenv("NSGA3_PAIRWISE")
+    w = workloads.make(name, N=N)
+    g = gpu_select(w.objs, w.refs, w.K, ctx=ctx)
+    _zero(compare_full(w.objs, w.refs, w.K, g))
+    ctx.close()
+
+
+@pytest.mark.parametrize("tail_block,levels", [(True, 2), (False, 1), (True, 5)])
+def test_peeling_tails(tail_block, levels, monkeypatch):
+    """Levels beyond the enqueued ones are finished by the cooperative tail or
+    by the single-workgroup tail; both must give the oracle's ranks."""
+    import paper_2503_20286_amd as nsga3
+    monkeypatch.setenv("NSGA3_TAIL_BLOCK", "1" if tail_block else "0")
+    monkeypatch.setenv("NSGA3_HOST_LEVELS", str(levels))
+    ctx = nsga3.Context(0)
+    monkeypatch.delenv("NSGA3_TAIL_BLOCK")
+    monkeypatch.delenv("NSGA3_HOST_LEVELS")
+    for name, N in (("ties", 4000), ("large", 3000)):
+        w = workloads.make(name, N=N)
+        g = gpu_select(w.objs, w.refs, w.K, ctx=ctx)
+        _zero(compare_full(w.objs, w.refs, w.K, g))
+    t = np.arange(300, dtype=np.float32)
+    F = np.stack([t, 2 * t + 1, t + 3], axis=1)[np.random.default_rng(2).permutation(300)]
+    R = workloads.das_dennis(3, 4).astype(np.float32)
+    g = gpu_select(F, R, 150, ctx=ctx)
+    assert g["info"].num_fronts == 300
+    _zero(compare_full(F, R, 150, g))
+    ctx.close()
