@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--precision-report", action="store_true",
                     help="instead of the throughput line: float32 vs bfloat16 association on the "
                          "workload, errors against the float64 oracle and the phase times")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched measurement (512 selections in one graph launch)")
+    ap.add_argument("--batch", type=int, default=512, help="instances in the batched plan")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (three times), to scale "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -132,6 +135,70 @@ def precision_report(args, w, objs, refs):
         "modes": out,
     }
     print(json.dumps(line), flush=True)
+
+
+def batched(args):
+    """Batched form: ``args.batch`` independent selections (N_b uniform in
+    [200, 20000], M_b from {2, 3, 5}, K_b = N_b/2) captured once into a plan
+    and replayed; compared with the same instances as back-to-back single
+    calls on one stream."""
+    import torch
+
+    import paper_2503_20286_amd as nsga3
+    import workloads
+    ws = workloads.make_batch(args.batch)
+    probs = [(torch.from_numpy(w.objs).cuda(), torch.from_numpy(w.refs).cuda(), w.K) for w in ws]
+    ctx = nsga3.Context(0)
+    ctx.reserve(max(w.N for w in ws), 5, 210)
+    t0 = time.perf_counter()
+    plan = nsga3.Plan(probs, ctx=ctx)
+    t_create = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    for _ in range(max(args.warmup, 1)):
+        plan.launch(stream)
+    torch.cuda.synchronize()
+    bad = [b for b, r in enumerate(plan.results) if r.info().status != 0]
+    if bad:
+        raise SystemExit(f"batched selection reported a status on instances {bad[:8]}")
+    steps = max(1, args.steps // 2)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        plan.launch(stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = start.elapsed_time(stop) / steps
+    # the same instances as single calls, one after another
+    outs = [nsga3.select(o, r, K, ctx=ctx) for (o, r, K) in probs]
+    torch.cuda.synchronize()
+    start.record(stream)
+    for (o, r, K), out in zip(probs, outs):
+        nsga3.select(o, r, K, ctx=ctx, out=out)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_single = start.elapsed_time(stop)
+    same = all(torch.equal(a.selected, b.selected) and torch.equal(a.rank, b.rank)
+               for a, b in zip(plan.results, outs))
+    info = plan.info()
+    plan.close()
+    n_pts = sum(w.N for w in ws)
+    return {
+        "value": args.batch / (ms_graph / 1e3),
+        "unit": "selections/s",
+        "ms_per_launch": ms_graph,
+        "points_per_s": n_pts / (ms_graph / 1e3),
+        "instances": args.batch,
+        "total_points": n_pts,
+        "graph_branches": info["branches"],
+        "graph_nodes": info["nodes"],
+        "plan_create_s": t_create,
+        "single_calls_ms": ms_single,
+        "single_calls_sel_per_s": args.batch / (ms_single / 1e3),
+        "speedup_vs_single_calls": ms_single / ms_graph,
+        "identical_to_single_calls": bool(same),
+        "steps": steps,
+    }
 
 
 def main():
@@ -249,6 +316,8 @@ def main():
                    "near_ties": info.near_ties, "intercept_fallback": info.intercept_fallback},
         "host_wall_s": t_host,
     }
+    if not args.no_batch:
+        res["batched"] = batched(args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.workload, N, min(args.cpu_sample_n, N))
     print(json.dumps(res), flush=True)

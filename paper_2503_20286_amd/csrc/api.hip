@@ -8,6 +8,7 @@
 #include <new>
 #include <vector>
 
+#include "engine.h"
 #include "kernels.h"
 
 using namespace nsga3;
@@ -16,6 +17,11 @@ struct nsga3_plan {
     int device = 0;
     int branches = 0;
     int64_t nodes = 0;
+    bool engine = false;                 // batched engine (else a graph of single selections)
+    void *ews = nullptr;                 // engine: every instance's workspace
+    nsga3::EInst *d_inst = nullptr;      // engine: instance table (sorted by M)
+    nsga3::EState *d_state = nullptr;
+    nsga3::EGlobal *d_glob = nullptr;    // one per objective count
     std::vector<void *> ws;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
@@ -502,7 +508,118 @@ static void plan_free(nsga3_plan *pl) {
     if (pl->cap) (void)hipStreamDestroy(pl->cap);
     for (void *w : pl->ws)
         if (w) (void)hipFree(w);
+    if (pl->ews) (void)hipFree(pl->ews);
+    if (pl->d_inst) (void)hipFree(pl->d_inst);
+    if (pl->d_state) (void)hipFree(pl->d_state);
+    if (pl->d_glob) (void)hipFree(pl->d_glob);
     delete pl;
+}
+
+// Batched plan through the engine: instances sorted by M, one persistent
+// engine launch per objective count (on forked streams), all captured with
+// the reset kernel into one graph.
+static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *probs, int32_t B,
+                                       nsga3_plan *pl) {
+    using namespace nsga3;
+    std::vector<int32_t> order(B);
+    for (int32_t b = 0; b < B; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return probs[x].M < probs[y].M; });
+    std::vector<EInst> inst(B);
+    std::vector<size_t> off(B);
+    size_t total = 0;
+    for (int32_t q = 0; q < B; ++q) {
+        const nsga3_problem &p = probs[order[q]];
+        off[q] = total;
+        total += (elayout(p.N, p.M, p.H).total + 255) & ~(size_t)255;
+    }
+    if (ctx->opt.max_workspace_bytes && total > ctx->opt.max_workspace_bytes) return NSGA3_E_NOMEM;
+    if (getenv("NSGA3_TEST_FAIL_ALLOC")) return NSGA3_E_NOMEM;
+    if (hipMalloc(&pl->ews, total) != hipSuccess ||
+        hipMalloc((void **)&pl->d_inst, sizeof(EInst) * (size_t)B) != hipSuccess ||
+        hipMalloc((void **)&pl->d_state, sizeof(EState) * (size_t)B) != hipSuccess) {
+        (void)hipGetLastError();
+        return NSGA3_E_NOMEM;
+    }
+    int pa_items = 32;
+    if (const char *e = getenv("NSGA3_ENGINE_PA_ITEMS")) {
+        const int v = atoi(e);
+        if (v >= 1 && v <= 1 << 20) pa_items = v;
+    }
+    std::vector<std::pair<int32_t, int32_t>> cls;  // (first instance, count) per M
+    for (int32_t q = 0; q < B; ++q) {
+        const nsga3_problem &p = probs[order[q]];
+        EInst &e = inst[q];
+        e.objs = p.objs;
+        e.refs = p.refs;
+        e.selected = p.selected;
+        e.rank = p.rank;
+        e.niche = p.niche;
+        e.dist = p.dist;
+        e.dom_in = p.dom_in;
+        e.dom_out = p.dom_out;
+        e.info = p.info;
+        e.ws = (char *)pl->ews + off[q];
+        e.K = p.K;
+        e.N = (int32_t)p.N;
+        e.M = p.M;
+        e.H = p.H;
+        e.pa_items = pa_items;
+        e.L = elayout(p.N, p.M, p.H);
+        if (q == 0 || p.M != probs[order[q - 1]].M) cls.push_back({q, 0});
+        cls.back().second++;
+    }
+    const int nclass = (int)cls.size();
+    if (hipMalloc((void **)&pl->d_glob, sizeof(EGlobal) * (size_t)nclass) != hipSuccess) {
+        (void)hipGetLastError();
+        return NSGA3_E_NOMEM;
+    }
+    if (hipMemcpy(pl->d_inst, inst.data(), sizeof(EInst) * (size_t)B, hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return NSGA3_E_HIP;
+    hipError_t e = hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking);
+    for (int c = 0; c < nclass && e == hipSuccess; ++c) {
+        hipStream_t bs;
+        e = hipStreamCreateWithFlags(&bs, hipStreamNonBlocking);
+        if (e == hipSuccess) pl->streams.push_back(bs);
+    }
+    for (int c = 0; c <= nclass && e == hipSuccess; ++c) {
+        hipEvent_t ev;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) pl->events.push_back(ev);
+    }
+    if (e != hipSuccess) return NSGA3_E_HIP;
+    pl->branches = nclass;
+    e = hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = engine_init(pl->d_inst, pl->d_state, pl->d_glob, B, nclass, pl->cap);
+    if (e == hipSuccess) e = hipEventRecord(pl->events[nclass], pl->cap);
+    for (int c = 0; c < nclass && e == hipSuccess; ++c) {
+        const int M = inst[cls[c].first].M;
+        int bpc = engine_blocks_per_cu(M);
+        if (bpc < 1) bpc = 1;
+        const int grid = ctx->num_cus * bpc;
+        e = hipStreamWaitEvent(pl->streams[c], pl->events[nclass], 0);
+        if (e == hipSuccess)
+            e = engine_launch(M, pl->d_inst, pl->d_state, cls[c].first, cls[c].second,
+                              pl->d_glob + c, grid, pl->streams[c]);
+        if (e == hipSuccess) e = hipEventRecord(pl->events[c], pl->streams[c]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(pl->cap, pl->events[c], 0);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(pl->cap, &graph);
+    if (e == hipSuccess) e = e2;
+    pl->graph = graph;
+    if (e == hipSuccess) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) {
+        size_t nn = 0;
+        if (hipGraphGetNodes(pl->graph, nullptr, &nn) == hipSuccess) pl->nodes = (int64_t)nn;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return NSGA3_E_HIP;
+    }
+    pl->engine = true;
+    return NSGA3_OK;
 }
 
 nsga3_status nsga3_plan_create(nsga3_ctx *ctx, const nsga3_problem *probs, int32_t B,
@@ -515,6 +632,16 @@ nsga3_status nsga3_plan_create(nsga3_ctx *ctx, const nsga3_problem *probs, int32
     nsga3_plan *pl = new (std::nothrow) nsga3_plan();
     if (!pl) return NSGA3_E_NOMEM;
     pl->device = ctx->device;
+    const char *mode = getenv("NSGA3_PLAN_MODE");
+    if (!(mode && strcmp(mode, "graph") == 0)) {
+        const nsga3_status st = plan_create_engine(ctx, probs, B, pl);
+        if (st != NSGA3_OK) {
+            plan_free(pl);
+            return st;
+        }
+        *out = pl;
+        return NSGA3_OK;
+    }
     int nbr = kPlanBranches;
     if (const char *e = getenv("NSGA3_PLAN_BRANCHES")) {
         const int v = atoi(e);

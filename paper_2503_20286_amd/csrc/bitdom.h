@@ -23,8 +23,8 @@ __host__ __device__ constexpr int blk_key_off(int k) { return 68 + 64 * k; }
 __host__ __device__ constexpr int blk_pm_off(int M, int k) { return 68 + 64 * M + 130 * k; }
 __host__ __device__ constexpr int blk_stride(int M) { return ((68 + 194 * M) + 3) / 4 * 4; }
 
-// Number of the 64 sorted keys S that are <= x (S padded with 0xffffffff, and
-// x is always below the padding).
+// Number of the 64 sorted keys S that are <= x, in [0, 64] (S padded with
+// 0xffffffff, and x is always below the padding).
 __device__ __forceinline__ uint32_t count_le64(const uint32_t *S, uint32_t x) {
     uint32_t c = (S[31] <= x) ? 32u : 0u;
     c += (S[c + 15] <= x) ? 16u : 0u;
@@ -32,6 +32,7 @@ __device__ __forceinline__ uint32_t count_le64(const uint32_t *S, uint32_t x) {
     c += (S[c + 3] <= x) ? 4u : 0u;
     c += (S[c + 1] <= x) ? 2u : 0u;
     c += (S[c] <= x) ? 1u : 0u;
+    c += (c == 63u && S[63] <= x) ? 1u : 0u;  // six halvings reach 63 at most
     return c;
 }
 
@@ -43,6 +44,7 @@ __device__ __forceinline__ uint32_t count_lt64(const uint32_t *S, uint32_t x) {
     c += (S[c + 3] < x) ? 4u : 0u;
     c += (S[c + 1] < x) ? 2u : 0u;
     c += (S[c] < x) ? 1u : 0u;
+    c += (c == 63u && S[63] < x) ? 1u : 0u;
     return c;
 }
 
@@ -54,6 +56,7 @@ __device__ __forceinline__ uint32_t count_pos_lt64(const int32_t *P, int32_t bou
     c += (P[c + 3] < bound) ? 4u : 0u;
     c += (P[c + 1] < bound) ? 2u : 0u;
     c += (P[c] < bound) ? 1u : 0u;
+    c += (c == 63u && P[63] < bound) ? 1u : 0u;
     return c;
 }
 

@@ -24,6 +24,7 @@
 
 #include "kernels.h"
 #include "prims.h"
+#include "stage_math.h"
 
 namespace nsga3 {
 
@@ -93,26 +94,12 @@ __global__ void k_refs(const float *__restrict__ refs, int H, int M, double *__r
         for (int k = 0; k < KP; ++k) rhat16[(int64_t)j * KP + k] = 0;
     }
     if (j >= H) return;
-    double nn = 0.0;
-    bool bad = false;
-    for (int k = 0; k < M; ++k) {
-        const float f = refs[(int64_t)j * M + k];
-        bad |= !__builtin_isfinite(f) || f < 0.0f;
-        const double v = (double)f;
-        nn = nn + v * v;
-    }
-    const double n = sqrt(nn);
-    bad |= !(n > 0.0) || !__builtin_isfinite(n);
-    if (bad) {
+    if (!unit_reference(refs, j, M, rhat64, rhat32)) {
         atomicOr(&sc->err, (uint32_t)kErrBadRef);
         return;
     }
-    for (int k = 0; k < M; ++k) {
-        const double r = (double)refs[(int64_t)j * M + k] / n;
-        rhat64[(int64_t)j * M + k] = r;
-        rhat32[(int64_t)j * M + k] = (float)r;
-        if (rhat16) rhat16[(int64_t)j * KP + k] = bf16_rne((float)r);
-    }
+    if (rhat16)
+        for (int k = 0; k < M; ++k) rhat16[(int64_t)j * KP + k] = bf16_rne(rhat32[(int64_t)j * M + k]);
 }
 
 __device__ __forceinline__ double ideal(const DevScalars *sc, int k) {
@@ -145,24 +132,8 @@ __global__ __launch_bounds__(kNormThreads) void k_extreme_partial(
         if (rank[i] > l) continue;
         double g[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            g[k] = k < M ? (double)objs[i * M + k] - z[k] : 0.0;
-            if (k < M && g[k] > nad[k]) nad[k] = g[k];
-        }
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            if (j < M) {
-                double asf = -DBL_MAX;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    if (k < M) {
-                        const double v = (k == j) ? g[k] : g[k] * 1e6;
-                        if (v > asf) asf = v;
-                    }
-                }
-                if (asf < best[j]) { best[j] = asf; bidx[j] = (int32_t)i; }
-            }
-        }
+        for (int k = 0; k < 16; ++k) g[k] = k < M ? (double)objs[i * M + k] - z[k] : 0.0;
+        asf_fold<16>(g, M, (int32_t)i, best, bidx, nad);
     }
     const int w = threadIdx.x / kWave;
 #pragma unroll
@@ -230,63 +201,9 @@ __global__ __launch_bounds__(64) void k_solve(const float *__restrict__ objs, in
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    double z[16];
+    double z[16], a[16];
     for (int k = 0; k < M; ++k) { z[k] = ideal(sc, k); sc->z[k] = z[k]; }
-    double A[16 * 16], rhs[16], b[16], a[16];
-    double maxabs = 0.0;
-    for (int j = 0; j < M; ++j) {
-        for (int k = 0; k < M; ++k) {
-            const double e = (double)objs[(int64_t)s_e[j] * M + k] - z[k];
-            A[j * M + k] = e;
-            const double v = fabs(e);
-            if (v > maxabs) maxabs = v;
-        }
-        rhs[j] = 1.0;
-    }
-    bool ok = maxabs > 0.0;
-    for (int c = 0; c < M && ok; ++c) {
-        int p = c;
-        double pv = fabs(A[c * M + c]);
-        for (int r = c + 1; r < M; ++r) {
-            const double v = fabs(A[r * M + c]);
-            if (v > pv) { pv = v; p = r; }
-        }
-        if (!(pv > 1e-10 * maxabs)) { ok = false; break; }
-        if (p != c) {
-            for (int k = 0; k < M; ++k) {
-                const double t = A[c * M + k];
-                A[c * M + k] = A[p * M + k];
-                A[p * M + k] = t;
-            }
-            const double t = rhs[c]; rhs[c] = rhs[p]; rhs[p] = t;
-        }
-        for (int r = c + 1; r < M; ++r) {
-            const double f = A[r * M + c] / A[c * M + c];
-            for (int k = c + 1; k < M; ++k) A[r * M + k] = A[r * M + k] - f * A[c * M + k];
-            A[r * M + c] = 0.0;
-            rhs[r] = rhs[r] - f * rhs[c];
-        }
-    }
-    if (ok) {
-        for (int c = M - 1; c >= 0; --c) {
-            double s = rhs[c];
-            for (int k = c + 1; k < M; ++k) s = s - A[c * M + k] * b[k];
-            b[c] = s / A[c * M + c];
-        }
-        for (int k = 0; k < M && ok; ++k) {
-            if (!(__builtin_isfinite(b[k]) && b[k] > 0.0)) { ok = false; break; }
-            const double ak = 1.0 / b[k];
-            if (!__builtin_isfinite(ak)) { ok = false; break; }
-            a[k] = ak;
-        }
-    }
-    int fb = 0;
-    if (!ok) {
-        fb = 1;
-        for (int k = 0; k < M; ++k) a[k] = s_nadir[k];
-    }
-    for (int k = 0; k < M; ++k)
-        if (a[k] == 0.0) { a[k] = 1.0; fb = 2; }
+    const int fb = solve_intercepts(objs, M, s_e, s_nadir, z, a);
     for (int k = 0; k < M; ++k) sc->a[k] = a[k];
     sc->fallback = fb;
 }
@@ -326,55 +243,14 @@ __global__ __launch_bounds__(kNormThreads) void k_associate(
     }
     double fp[M];
     float y[M];
-    double mx = 0.0;
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        fp[k] = ((double)objs[i * M + k] - sc->z[k]) / sc->a[k];
-        mx = fp[k] > mx ? fp[k] : mx;
-    }
-    float l1 = 0.0f;
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        y[k] = mx > 0.0 ? (float)(fp[k] / mx) : 0.0f;
-        l1 += y[k];
-    }
-    // screening: s_j = y . rhat_j in float32 (the scale of y does not move argmax)
-    float smax = -FLT_MAX;
-    for (int j = 0; j < H; ++j) {
-        float s = 0.0f;
-#pragma unroll
-        for (int k = 0; k < M; ++k) s = __fmaf_rn(y[k], R[j * M + k], s);
-        smax = s > smax ? s : smax;
-    }
-    // |s32 - s| <= (M + 3) u ||y||_2 <= (M + 3) u ||y||_1 with u = 2^-24; keep a
-    // wide margin so every reference within float64 reach of the best survives
-    const float band = 4.0f * (float)(M + 4) * 5.9604645e-8f * l1 + 1e-30f;
-    const float thr = smax - band;
-    double d1 = DBL_MAX, d2 = DBL_MAX;
-    int32_t best = 0;
-    for (int j = 0; j < H; ++j) {
-        float s = 0.0f;
-#pragma unroll
-        for (int k = 0; k < M; ++k) s = __fmaf_rn(y[k], R[j * M + k], s);
-        if (s < thr) continue;
-        const double *rd = rhat64 + (int64_t)j * M;
-        double s64 = 0.0;
-#pragma unroll
-        for (int k = 0; k < M; ++k) s64 = s64 + fp[k] * rd[k];
-        double q = 0.0;
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const double e = fp[k] - s64 * rd[k];
-            q = q + e * e;
-        }
-        const double d = sqrt(q);
-        if (d < d1) { d2 = d1; d1 = d; best = j; }
-        else if (d < d2) { d2 = d; }
-    }
+    const float l1 = normalise_point<M>(objs + i * M, sc->z, sc->a, fp, y);
+    int32_t best;
+    double d1, d2;
+    associate_point<M>(fp, y, l1, R, rhat64, H, best, d1, d2);
     niche[i] = best;
     if (dist) dist[i] = (float)d1;
     dist64[i] = d1;
-    if (d2 != DBL_MAX && (d2 - d1) < 1e-6 * fmax(d2, 1e-300)) atomicAdd(&sc->near_ties, 1);
+    if (near_tie(d1, d2)) atomicAdd(&sc->near_ties, 1);
     if (r < l) {
         atomicAdd(&rho[best], 1);
         selflag[i] = 1;
@@ -491,17 +367,7 @@ __global__ __launch_bounds__(256) void k_associate_bf16(
         for (int v = 0; v < 16; ++v) {
             const int j = tl * 32 + 8 * (v / 4) + 4 * half + (v % 4);
             if (j >= H || acc[v] < thr || !active) continue;
-            const double *rd = rhat64 + (int64_t)j * M;
-            double s64 = 0.0;
-#pragma unroll
-            for (int k = 0; k < M; ++k) s64 = s64 + fp[k] * rd[k];
-            double q = 0.0;
-#pragma unroll
-            for (int k = 0; k < M; ++k) {
-                const double e = fp[k] - s64 * rd[k];
-                q = q + e * e;
-            }
-            const double d = sqrt(q);
+            const double d = line_distance<M>(fp, rhat64 + (int64_t)j * M);
             if (d < d1 || (d == d1 && j < best)) { d2 = d1; d1 = d; best = j; }
             else if (d < d2 || d == d2) { d2 = d < d2 ? d : d2; }
         }
@@ -528,7 +394,7 @@ __global__ __launch_bounds__(256) void k_associate_bf16(
     niche[i] = best;
     if (dist) dist[i] = (float)d1;
     dist64[i] = d1;
-    if (d2 != DBL_MAX && (d2 - d1) < 1e-6 * fmax(d2, 1e-300)) atomicAdd(&sc->near_ties, 1);
+    if (near_tie(d1, d2)) atomicAdd(&sc->near_ties, 1);
     if (r < l) {
         atomicAdd(&rho[best], 1);
         selflag[i] = 1;

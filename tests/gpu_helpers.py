@@ -31,6 +31,25 @@ def dist_close(d_gpu: np.ndarray, d_ref: np.ndarray, fp_norm: np.ndarray) -> np.
     return np.abs(d_gpu.astype(np.float64) - d_ref) <= 1e-5 * np.maximum(1.0, fp_norm)
 
 
+def line_distance64(objs, z, a, refs, ref_idx):
+    """Float64 residual distance ||f' - (f'.r) r|| of each row to reference
+    ref_idx[row], summed left to right as the library and the oracle do."""
+    f = (objs.astype(np.float64) - z) / a
+    R = refs.astype(np.float64)[ref_idx]
+    nn = np.zeros(len(f))
+    for k in range(R.shape[1]):
+        nn = nn + R[:, k] * R[:, k]
+    r = R / np.sqrt(nn)[:, None]
+    s = np.zeros(len(f))
+    for k in range(R.shape[1]):
+        s = s + f[:, k] * r[:, k]
+    q = np.zeros(len(f))
+    for k in range(R.shape[1]):
+        e = f[:, k] - s * r[:, k]
+        q = q + e * e
+    return np.sqrt(q)
+
+
 def compare_full(objs, refs, K, g, with_counts=True):
     """Element-by-element comparison with the oracle's whole selection.
     Returns a dict of mismatch counts (all must be zero)."""
@@ -60,10 +79,13 @@ def compare_full(objs, refs, K, g, with_counts=True):
     if not np.any(tie):
         rep["selected"] = int(not np.array_equal(g["selected"], s.selected))
     else:
-        # stage-wise: oracle niching on the GPU's association
+        # stage-wise: oracle niching on the GPU's association, with the float64
+        # distance of each near-tie point to the reference the GPU chose
         rho = oracle.niche_count(g["rank"], g["niche"], l, refs.shape[0])
         d64 = np.where(S, dist, -1.0)
-        d64[tie] = g["dist"][tie]
+        moved = tie & (g["niche"] != niche)
+        if np.any(moved):
+            d64[moved] = line_distance64(objs[moved], nz.z, nz.a, refs, g["niche"][moved])
         chosen = oracle.niching(g["rank"], g["niche"], d64, l, refs.shape[0], s.num_from_last, rho)
         want = np.nonzero((g["rank"] < l) | chosen)[0]
         rep["selected"] = int(not np.array_equal(g["selected"], want))

@@ -1,6 +1,7 @@
-"""GPU: batched plans (many selections in one graph launch) must reproduce the
-single-call results bit for bit, on every replay, with new data in the same
-buffers, and match the oracle."""
+"""GPU: batched plans (many selections in one graph launch).  Every output of
+every instance must equal a single nsga3_select call on the same instance, on
+every replay, with new data in the same buffers; sampled instances are also
+checked against the oracle."""
 from __future__ import annotations
 
 import numpy as np
@@ -25,30 +26,53 @@ def _gpu():
     oracle.lib()
 
 
+@pytest.fixture(params=["engine", "graph"])
+def plan_mode(request, monkeypatch):
+    if request.param == "graph":
+        monkeypatch.setenv("NSGA3_PLAN_MODE", "graph")
+    else:
+        monkeypatch.delenv("NSGA3_PLAN_MODE", raising=False)
+    return request.param
+
+
 def _host(sel):
     return {k: None if getattr(sel, k) is None else getattr(sel, k).cpu().numpy() for k in FIELDS}
 
 
-def _make(B, seed, n_hi=3000):
-    return workloads.make_batch(B, n_lo=1, n_hi=n_hi, base_seed=seed)
+def _dev(ws):
+    import torch
+    return [(torch.from_numpy(w.objs).cuda(), torch.from_numpy(w.refs).cuda(), w.K) for w in ws]
 
 
-def test_plan_matches_single_calls_and_oracle():
+def _check_against_single(plan, probs, tag):
     import torch
     import paper_2503_20286_amd as nsga3
-    ws = _make(24, 7000)
-    probs = [(torch.from_numpy(w.objs).cuda(), torch.from_numpy(w.refs).cuda(), w.K) for w in ws]
+    for b, (o, r, K) in enumerate(probs):
+        single = nsga3.select(o, r, K)
+        torch.cuda.synchronize()
+        a, s = _host(plan.results[b]), _host(single)
+        for k in FIELDS:
+            assert np.array_equal(a[k], s[k]), (tag, b, k)
+        ia, is_ = plan.results[b].info(), single.info()
+        assert (ia.status, ia.last_front, ia.num_fronts, ia.last_front_size, ia.num_from_last,
+                ia.intercept_fallback, ia.near_ties) == \
+               (is_.status, is_.last_front, is_.num_fronts, is_.last_front_size,
+                is_.num_from_last, is_.intercept_fallback, is_.near_ties), (tag, b)
+
+
+def test_plan_matches_single_calls_and_oracle(plan_mode):
+    import torch
+    import paper_2503_20286_amd as nsga3
+    ws = workloads.make_batch(24, n_lo=1, n_hi=3000, base_seed=7000)
+    probs = _dev(ws)
+    print("plan", plan_mode, flush=True)
     plan = nsga3.Plan(probs)
-    print("plan", plan.info(), flush=True)
+    print("plan info", plan.info(), flush=True)
     for rep in range(3):  # several replays, each checked
         plan.launch()
         torch.cuda.synchronize()
-        for b, (o, r, K) in enumerate(probs):
-            single = nsga3.select(o, r, K)
-            torch.cuda.synchronize()
-            a, s = _host(plan.results[b]), _host(single)
-            for k in FIELDS:
-                assert np.array_equal(a[k], s[k]), (rep, b, k)
+        _check_against_single(plan, probs, (plan_mode, rep))
+        for b in range(len(probs)):
             assert plan.results[b].info().status == 0
     for b in (0, 5, 23):
         w = ws[b]
@@ -59,11 +83,11 @@ def test_plan_matches_single_calls_and_oracle():
     plan.close()
 
 
-def test_plan_replay_with_new_data_in_same_buffers():
+def test_plan_replay_with_new_data_in_same_buffers(plan_mode):
     import torch
     import paper_2503_20286_amd as nsga3
-    ws = _make(12, 8000)
-    probs = [(torch.from_numpy(w.objs).cuda(), torch.from_numpy(w.refs).cuda(), w.K) for w in ws]
+    ws = workloads.make_batch(12, n_lo=1, n_hi=3000, base_seed=8000)
+    probs = _dev(ws)
     plan = nsga3.Plan(probs)
     plan.launch()
     torch.cuda.synchronize()
@@ -72,14 +96,68 @@ def test_plan_replay_with_new_data_in_same_buffers():
         o.copy_(torch.from_numpy(w.objs).cuda())
     torch.cuda.synchronize()
     for rep in range(2):
+        x = torch.ones(1 << 20, device="cuda")  # eager work between replays
+        (x * 2).sum().item()
         plan.launch()
         torch.cuda.synchronize()
-        for b, (o, r, K) in enumerate(probs):
+        _check_against_single(plan, probs, (plan_mode, "new", rep))
+    plan.close()
+
+
+def test_engine_edge_instances():
+    """Mixed objective counts in one plan (one engine launch per M), sizes 1,
+    2, ragged tile boundaries, duplicates, K = 1 and K = N, and a long chain."""
+    import torch
+    import paper_2503_20286_amd as nsga3
+    rng = np.random.default_rng(11)
+    cases = []
+    for (N, M) in [(1, 2), (2, 3), (3, 5), (64, 4), (1023, 2), (1024, 3), (1025, 5), (2049, 7),
+                   (4097, 2), (700, 16), (300, 9)]:
+        f = rng.integers(0, 6, size=(N, M)).astype(np.float32)  # ties and duplicates
+        refs = workloads.das_dennis(M, 3 if M <= 5 else 1).astype(np.float32)
+        for K in sorted({1, max(1, N // 3), N}):
+            cases.append((f, refs, K))
+    a = np.arange(600, dtype=np.float32)
+    chain = np.stack([a, a], axis=1)  # a total order: 600 fronts
+    cases.append((chain, workloads.das_dennis(2, 5).astype(np.float32), 300))
+    probs = [(torch.from_numpy(np.ascontiguousarray(f)).cuda(),
+              torch.from_numpy(np.ascontiguousarray(r)).cuda(), K) for (f, r, K) in cases]
+    plan = nsga3.Plan(probs)
+    plan.launch()
+    torch.cuda.synchronize()
+    _check_against_single(plan, probs, "edge")
+    for b, (f, r, K) in enumerate(cases):
+        g = _host(plan.results[b])
+        g["info"] = plan.results[b].info()
+        rep = compare_full(f, r, K, g)
+        assert not {k: v for k, v in rep.items() if k != "near_ties" and v}, (b, rep)
+    plan.close()
+
+
+def test_engine_bad_instance_is_isolated():
+    """A non-finite objective or a bad reference row in one instance sets that
+    instance's status and leaves every other instance exact."""
+    import torch
+    import paper_2503_20286_amd as nsga3
+    ws = workloads.make_batch(6, n_lo=100, n_hi=900, base_seed=8100)
+    probs = _dev(ws)
+    probs[1][0][3, 0] = float("nan")
+    probs[4][1][2, 0] = -1.0
+    plan = nsga3.Plan(probs)
+    plan.launch()
+    torch.cuda.synchronize()
+    for b in range(len(probs)):
+        st = plan.results[b].info().status
+        if b in (1, 4):
+            assert st == -2, (b, st)  # NSGA3_E_NONFINITE
+        else:
+            assert st == 0
+            o, r, K = probs[b]
             single = nsga3.select(o, r, K)
             torch.cuda.synchronize()
             a, s = _host(plan.results[b]), _host(single)
             for k in FIELDS:
-                assert np.array_equal(a[k], s[k]), (rep, b, k)
+                assert np.array_equal(a[k], s[k]), (b, k)
     plan.close()
 
 
