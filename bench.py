@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched measurement (512 selections in one graph launch)")
     ap.add_argument("--batch", type=int, default=512, help="instances in the batched plan")
+    ap.add_argument("--engine-stats", action="store_true",
+                    help="add the batched engine's per-stage block times (separate plan)")
+    ap.add_argument("--plan-compare", action="store_true",
+                    help="also time the batch as a graph of single selections")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (three times), to scale "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -183,6 +187,36 @@ def batched(args):
     info = plan.info()
     plan.close()
     n_pts = sum(w.N for w in ws)
+    extra = {}
+    if args.engine_stats:
+        pctx = nsga3.Context(0)
+        pctx.profile(True)
+        p2 = nsga3.Plan(probs, ctx=pctx)
+        for _ in range(2):
+            p2.launch(stream)
+        torch.cuda.synchronize()
+        st = p2.stage_times()
+        extra["engine_block_ms_per_launch"] = {
+            "stages": {k: {"item": v["item_ms"] / 2, "epilogue": v["epilogue_ms"] / 2,
+                           "items": v["items"] // 2} for k, v in st["stages"].items()},
+            "probe": st["probe_ms"] / 2, "idle": st["idle_ms"] / 2}
+        p2.close()
+        pctx.close()
+    if args.plan_compare:
+        os.environ["NSGA3_PLAN_MODE"] = "graph"
+        try:
+            p3 = nsga3.Plan(probs, ctx=ctx)
+        finally:
+            del os.environ["NSGA3_PLAN_MODE"]
+        p3.launch(stream)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(steps):
+            p3.launch(stream)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        extra["graph_of_single_calls_ms"] = start.elapsed_time(stop) / steps
+        p3.close()
     return {
         "value": args.batch / (ms_graph / 1e3),
         "unit": "selections/s",
@@ -198,6 +232,7 @@ def batched(args):
         "speedup_vs_single_calls": ms_single / ms_graph,
         "identical_to_single_calls": bool(same),
         "steps": steps,
+        **extra,
     }
 
 

@@ -151,14 +151,20 @@ typedef struct nsga3_plan nsga3_plan;
 
 /*
  * Build a plan for B problems (probs: host array of B descriptors).  The plan
- * allocates its own workspaces, picks per-problem launch shapes (see
- * NSGA3_TUNE below), and captures every selection into one HIP graph whose
- * branches run problems concurrently.  Synchronous; allocates.  The buffer
- * pointers are baked into the graph: the caller keeps them alive and may
- * rewrite their contents between launches.  Results of a launch are
- * identical to running nsga3_select on each problem.
+ * allocates one workspace per problem and captures, into one HIP graph, a
+ * reset kernel and one persistent engine launch per distinct M (on parallel
+ * graph branches).  An engine launch runs every problem of its M through all
+ * stages of the selection as independent work items, so problems of very
+ * different sizes and front counts share the GPU without per-problem
+ * launches.  Synchronous; allocates.  The buffer pointers are baked into the
+ * graph: the caller keeps them alive and may rewrite their contents between
+ * launches.  Results of a launch are identical to running nsga3_select on
+ * each problem; a problem whose data is bad (non-finite, bad reference row)
+ * reports it in its own info and does not disturb the others.
  * Errors: NSGA3_E_INVALID for a bad descriptor (nothing is built),
  * NSGA3_E_NOMEM / NSGA3_E_HIP when allocation or capture fails.
+ * When the context has profiling enabled (nsga3_profile) at creation, the
+ * plan also collects the stage diagnostics of nsga3_plan_stage_times.
  */
 nsga3_status nsga3_plan_create(nsga3_ctx *ctx, const nsga3_problem *probs, int32_t B,
                                nsga3_plan **out);
@@ -172,6 +178,25 @@ nsga3_status nsga3_plan_info(const nsga3_plan *plan, int32_t *branches, int64_t 
 /* Free the plan (graph, workspaces).  The caller must make sure no launch of
  * the plan is still running.  NULL is ignored. */
 void nsga3_plan_destroy(nsga3_plan *plan);
+
+/* Engine stages (index into the arrays of nsga3_plan_stage_times):
+ *   0 keys and references, 1 radix histogram, 2 radix scatter, 3 sorted records,
+ *   4 dominance counts, 5 split counts, 6 split writes, 7 peeling decrements,
+ *   8 outputs in original order, 9 extreme points, 10 association,
+ *   11 bucket scatter, 12 niche picks, 13 compaction counts, 14 compaction
+ *   writes, 15 short-list split in one item, 16 done. */
+#define NSGA3_PLAN_STAGES 17
+
+/* Diagnostics of a plan created while profiling was enabled: per stage, the
+ * block-milliseconds spent inside its work items and its epilogues, and the
+ * number of items run; plus block-milliseconds spent finding work (probe) and
+ * finding none (idle).  Sums over every worker block and every launch since
+ * creation.  Synchronises the device.  Arrays are host double / int64_t
+ * [NSGA3_PLAN_STAGES]; any pointer may be NULL.  NSGA3_E_UNSUPPORTED when the
+ * plan collects no diagnostics. */
+nsga3_status nsga3_plan_stage_times(const nsga3_plan *plan, double *item_ms,
+                                    double *epilogue_ms, int64_t *items, double *probe_ms,
+                                    double *idle_ms);
 
 /* Phases of one nsga3_select call, for nsga3_phase_times. */
 #define NSGA3_NUM_PHASES 6

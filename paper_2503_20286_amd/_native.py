@@ -42,6 +42,12 @@ class _Options(ctypes.Structure):
                 ("max_workspace_bytes", ctypes.c_size_t)]
 
 
+PLAN_STAGES = ("keys_refs", "radix_hist", "radix_scatter", "records", "dominance",
+               "split_count", "split_write", "peel_decrements", "orig_order", "extremes",
+               "association", "bucket_scatter", "niche_picks", "compact_count", "compact_write",
+               "split_one", "done")
+
+
 class _Problem(ctypes.Structure):
     _fields_ = [("objs", ctypes.c_void_p), ("N", ctypes.c_int64), ("M", ctypes.c_int32),
                 ("refs", ctypes.c_void_p), ("H", ctypes.c_int32), ("K", ctypes.c_int64),
@@ -92,6 +98,11 @@ def load():
         L.nsga3_plan_launch.restype = ctypes.c_int
         L.nsga3_plan_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         L.nsga3_plan_info.restype = ctypes.c_int
+        L.nsga3_plan_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
+                                             ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double)]
+        L.nsga3_plan_stage_times.restype = ctypes.c_int
         L.nsga3_plan_destroy.argtypes = [P]
         L.nsga3_plan_destroy.restype = None
         L.nsga3_version.argtypes = []
@@ -327,6 +338,22 @@ class Plan:
         if rc != 0:
             raise NativeError("nsga3_plan_info", rc, self._lib)
         return {"branches": b.value, "nodes": n.value}
+
+    def stage_times(self):
+        """Engine diagnostics (plan created while ctx profiling was on): per
+        stage block-ms in items and epilogues, item counts; probe / idle block-ms."""
+        n = len(PLAN_STAGES)
+        it = (ctypes.c_double * n)()
+        ep = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        pr = ctypes.c_double()
+        idl = ctypes.c_double()
+        rc = self._lib.nsga3_plan_stage_times(self._h, it, ep, cnt, ctypes.byref(pr), ctypes.byref(idl))
+        if rc != 0:
+            raise NativeError("nsga3_plan_stage_times", rc, self._lib)
+        return {"stages": {PLAN_STAGES[q]: {"item_ms": it[q], "epilogue_ms": ep[q], "items": cnt[q]}
+                           for q in range(n) if cnt[q] or ep[q]},
+                "probe_ms": pr.value, "idle_ms": idl.value}
 
     def launch(self, stream=None):
         import torch

@@ -22,6 +22,8 @@ struct nsga3_plan {
     nsga3::EInst *d_inst = nullptr;      // engine: instance table (sorted by M)
     nsga3::EState *d_state = nullptr;
     nsga3::EGlobal *d_glob = nullptr;    // one per objective count
+    nsga3::EStats *d_stats = nullptr;    // engine diagnostics (plans created while profiling)
+    int clock_khz = 0;
     std::vector<void *> ws;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
@@ -512,6 +514,7 @@ static void plan_free(nsga3_plan *pl) {
     if (pl->d_inst) (void)hipFree(pl->d_inst);
     if (pl->d_state) (void)hipFree(pl->d_state);
     if (pl->d_glob) (void)hipFree(pl->d_glob);
+    if (pl->d_stats) (void)hipFree(pl->d_stats);
     delete pl;
 }
 
@@ -577,6 +580,15 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
     if (hipMemcpy(pl->d_inst, inst.data(), sizeof(EInst) * (size_t)B, hipMemcpyHostToDevice) !=
         hipSuccess)
         return NSGA3_E_HIP;
+    if (ctx->profiling) {
+        if (hipMalloc((void **)&pl->d_stats, sizeof(EStats)) != hipSuccess ||
+            hipMemset(pl->d_stats, 0, sizeof(EStats)) != hipSuccess ||
+            hipDeviceGetAttribute(&pl->clock_khz, hipDeviceAttributeWallClockRate, ctx->device) !=
+                hipSuccess) {
+            (void)hipGetLastError();
+            return NSGA3_E_NOMEM;
+        }
+    }
     hipError_t e = hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking);
     for (int c = 0; c < nclass && e == hipSuccess; ++c) {
         hipStream_t bs;
@@ -596,12 +608,16 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
     for (int c = 0; c < nclass && e == hipSuccess; ++c) {
         const int M = inst[cls[c].first].M;
         int bpc = engine_blocks_per_cu(M);
+        if (const char *ev = getenv("NSGA3_ENGINE_BLOCKS_PER_CU")) {
+            const int v = atoi(ev);
+            if (v >= 1 && v < bpc) bpc = v;
+        }
         if (bpc < 1) bpc = 1;
         const int grid = ctx->num_cus * bpc;
         e = hipStreamWaitEvent(pl->streams[c], pl->events[nclass], 0);
         if (e == hipSuccess)
             e = engine_launch(M, pl->d_inst, pl->d_state, cls[c].first, cls[c].second,
-                              pl->d_glob + c, grid, pl->streams[c]);
+                              pl->d_glob + c, pl->d_stats, grid, pl->streams[c]);
         if (e == hipSuccess) e = hipEventRecord(pl->events[c], pl->streams[c]);
         if (e == hipSuccess) e = hipStreamWaitEvent(pl->cap, pl->events[c], 0);
     }
@@ -746,6 +762,30 @@ nsga3_status nsga3_plan_info(const nsga3_plan *plan, int32_t *branches, int64_t 
     if (!plan) return NSGA3_E_INVALID;
     if (branches) *branches = plan->branches;
     if (nodes) *nodes = plan->nodes;
+    return NSGA3_OK;
+}
+
+static_assert(nsga3::kSDone + 1 == NSGA3_PLAN_STAGES, "stage list and header disagree");
+
+nsga3_status nsga3_plan_stage_times(const nsga3_plan *plan, double *item_ms, double *epilogue_ms,
+                                    int64_t *items, double *probe_ms, double *idle_ms) {
+    if (!plan) return NSGA3_E_INVALID;
+    if (!plan->d_stats || plan->clock_khz <= 0) return NSGA3_E_UNSUPPORTED;
+    DeviceGuard g(plan->device);
+    nsga3::EStats h;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(&h, plan->d_stats, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        return NSGA3_E_HIP;
+    }
+    const double per_ms = (double)plan->clock_khz;  // ticks per millisecond
+    for (int q = 0; q < NSGA3_PLAN_STAGES; ++q) {
+        if (item_ms) item_ms[q] = (double)h.item[q] / per_ms;
+        if (epilogue_ms) epilogue_ms[q] = (double)h.epilogue[q] / per_ms;
+        if (items) items[q] = (int64_t)h.items[q];
+    }
+    if (probe_ms) *probe_ms = (double)h.probe / per_ms;
+    if (idle_ms) *idle_ms = (double)h.idle / per_ms;
     return NSGA3_OK;
 }
 

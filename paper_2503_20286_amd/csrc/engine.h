@@ -36,8 +36,11 @@ enum EStage : int32_t {
     kSBRank,      // in-bucket ranks and picks
     kSCmpC,       // selection flags: per-item counts
     kSCmpW,       // selection flags: ordered write
+    kSSplit1,     // level split of a short list in one item (arg = level)
     kSDone,
 };
+
+constexpr int kESplitOne = 4 * kESplit;  // lists up to this length split in one item
 
 // Per-instance scalars (in the instance's workspace).
 struct EScal {
@@ -139,11 +142,20 @@ struct alignas(128) EGlobal {
     uint32_t pad[30];
 };
 
+// Optional diagnostics, summed over blocks and launches (wall-clock ticks).
+struct EStats {
+    unsigned long long item[kSDone + 1];      // inside items, per stage
+    unsigned long long epilogue[kSDone + 1];  // epilogues of completed stages
+    unsigned long long items[kSDone + 1];     // items run, per stage
+    unsigned long long probe;                 // successful searches for an item
+    unsigned long long idle;                  // searches that found nothing
+};
+
 // Launches (engine.hip).  Instances [b0, b0 + nb) of `inst` must share M.
 hipError_t engine_init(const EInst *inst, EState *st, EGlobal *g, int32_t B, int32_t nclass,
                        hipStream_t s);
 hipError_t engine_launch(int M, const EInst *inst, EState *st, int32_t b0, int32_t nb, EGlobal *g,
-                         int grid, hipStream_t s);
+                         EStats *stats, int grid, hipStream_t s);
 int engine_blocks_per_cu(int M);
 
 }  // namespace nsga3

@@ -11,8 +11,9 @@
 // of resident blocks makes progress, and blocks leave when every instance of
 // the launch is done (or after a long idle period, flagged as an error).
 //
-// Memory ordering: every wave of a finishing block issues an agent-scope
-// release fence before the block counts its item; the epilogue block
+// Memory ordering: every wave of a finishing block waits for its stores to
+// reach the L2, then one agent-scope release fence writes them back before the
+// block counts its item; the epilogue block
 // acquires before reading, and publishes the next stage with a release
 // store; claimers acquire after a successful claim.  Data written inside the
 // kernel is never read through the scalar cache (which vector stores do not
@@ -244,32 +245,31 @@ __device__ void item_recs(const EInst &I, int32_t t) {
     }
 }
 
-// a1: dominance counts of one (i-chunk, j-tile) pair of the triangle.
+// a1: dominance counts of one (i-chunk, j-tile) pair of the triangle.  The
+// records are written once per launch (before any item of this stage reads
+// them), so the earlier points stream through the scalar cache as in the
+// single-selection kernel.
+typedef __attribute__((address_space(4))) const uint32_t const_u32;
+
 template <int M>
 __device__ void item_dom(const EInst &I, int32_t b, uint32_t *smem) {
     const ELayout &L = I.L;
     constexpr int MP = rec_stride(M);
-    constexpr int IC = kJT < 8192 / MP ? kJT : 8192 / MP;
-    constexpr int R = kJT / IC;
+    constexpr int IC = kJT;
     char *w = I.ws;
     const int32_t N = I.N;
-    const uint32_t u = (uint32_t)b / R;
-    uint32_t jt = (uint32_t)((sqrtf(8.0f * (float)u + 1.0f) - 1.0f) * 0.5f);
-    while ((uint64_t)(jt + 1) * (jt + 2) / 2 <= u) ++jt;
-    while ((uint64_t)jt * (jt + 1) / 2 > u) --jt;
-    const int32_t ic = b - (int32_t)(R * (jt * (jt + 1) / 2));
+    uint32_t jt = (uint32_t)((sqrtf(8.0f * (float)b + 1.0f) - 1.0f) * 0.5f);
+    while ((uint64_t)(jt + 1) * (jt + 2) / 2 <= (uint32_t)b) ++jt;
+    while ((uint64_t)jt * (jt + 1) / 2 > (uint32_t)b) --jt;
+    const int32_t ic = b - (int32_t)(jt * (jt + 1) / 2);
     const int32_t i0 = ic * IC;
     const int32_t jt0 = (int32_t)jt * kJT;
     const uint32_t *recs = at<uint32_t>(w, L.recs);
+    const const_u32 *srec = (const const_u32 *)recs;
     const int32_t *runstart = at<int32_t>(w, L.runstart);
     int32_t *din = at<int32_t>(w, L.din), *dout = at<int32_t>(w, L.dout);
     if (i0 >= N) return;
-    const int32_t blk_hi = ld(&runstart[min(jt0 + kJT - 1, N - 1)]);
-    const int32_t i1 = min(min(i0 + IC, N), blk_hi);
-    if (i1 <= i0) return;  // no point of this chunk precedes the tile's runs
-    uint32_t *lrec = smem;
-    uint32_t *obuf = smem + IC * MP;  // [kWaves][IC]
-    stage_recs<MP>(lrec, recs + (size_t)i0 * MP, i1 - i0);
+    uint32_t *obuf = smem;  // [kWaves][IC]
     for (int x = threadIdx.x; x < kWaves * IC; x += kEThreads) obuf[x] = 0;
     __syncthreads();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -291,6 +291,7 @@ __device__ void item_dom(const EInst &I, int32_t b, uint32_t *smem) {
             run[t] = 0;
         }
     }
+    int32_t i1 = min(i0 + IC, N);
     if (jbase < N) {
         const int32_t qlast = min(jbase + kWave * kT - 1, N - 1);
         const int32_t run_lo = ld(&runstart[jbase]);
@@ -299,9 +300,10 @@ __device__ void item_dom(const EInst &I, int32_t b, uint32_t *smem) {
         const int32_t ifast = min(max(run_lo, i0), iend);
         const bool lane0 = lane == 0;
         if (ifast > i0)
-            tile_rows<M, false, true>(lrec, ifast - i0, kj, run, cin, obuf + wv * IC, lane0);
+            tile_rows<M, false, true>(srec + (size_t)i0 * MP, ifast - i0, kj, run, cin,
+                                      obuf + wv * IC, lane0);
         if (iend > ifast)
-            tile_rows<M, true, true>(lrec + (size_t)(ifast - i0) * MP, iend - ifast, kj, run, cin,
+            tile_rows<M, true, true>(srec + (size_t)ifast * MP, iend - ifast, kj, run, cin,
                                      obuf + wv * IC + (ifast - i0), lane0);
     }
     __syncthreads();
@@ -374,41 +376,80 @@ __device__ void item_splitc(const EInst &I, int32_t k, int32_t n, int32_t t,
     }
 }
 
-// Split, writing pass: ordered copy into F_k (rank k) and U_k.
+// Ordered split of list entries [e0, e1) (at most kESplit) into F_k (rank k)
+// and U_k at output offsets (of, ou); each thread owns kESplit / kEThreads
+// consecutive entries and one packed block scan gives every offset.  Returns
+// the chunk's front and remaining counts.
 template <int M>
-__device__ void item_splitw(const EInst &I, int32_t k, int32_t n, int32_t t,
-                            uint32_t *smem) {
-    const ELayout &L = I.L;
+__device__ void split_chunk(const LevelLists &s, int32_t k, int32_t e0, int32_t e1, uint32_t of,
+                            uint32_t ou, int32_t *rank_s, uint32_t *lds, uint32_t *nf,
+                            uint32_t *nu) {
     constexpr int MP = rec_stride(M);
+    constexpr int kPer = kESplit / kEThreads;
+    const int32_t t0 = e0 + (int32_t)threadIdx.x * kPer;
+    int32_t cnt[kPer];
+    uint32_t zf = 0, zu = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int32_t e = t0 + q;
+        cnt[q] = e < e1 ? s.scnt[e] : -1;
+        zf += cnt[q] == 0 ? 1u : 0u;
+        zu += (e < e1 && cnt[q] != 0) ? 1u : 0u;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan((zf << 16) | zu, lds, &tot);
+    uint32_t f = of + (ex >> 16), u = ou + (ex & 0xffffu);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int32_t e = t0 + q;
+        if (e >= e1) break;
+        const uint32_t *r = s.srec + (size_t)e * MP;
+        if (cnt[q] == 0) {
+            copy_rec<MP>(s.fdst + (size_t)f * MP, r);
+            rank_s[r[M]] = k;
+            ++f;
+        } else {
+            copy_rec<MP>(s.udst + (size_t)u * MP, r);
+            s.rdst[u] = s.srun[e];
+            s.cdst[u] = cnt[q];
+            ++u;
+        }
+    }
+    *nf = tot >> 16;
+    *nu = tot & 0xffffu;
+}
+
+// Split, writing pass of one item, at the offsets the counting pass scanned.
+template <int M>
+__device__ void item_splitw(const EInst &I, int32_t k, int32_t n, int32_t t, uint32_t *smem) {
+    const ELayout &L = I.L;
     char *w = I.ws;
     const LevelLists s = level_lists(w, L, k);
-    int32_t *rank_s = at<int32_t>(w, L.rank_s);
     const uint32_t *spc = at<uint32_t>(w, L.spc);
-    uint32_t of = ld(&spc[2 * t]), ou = ld(&spc[2 * t + 1]);
-    const int32_t s0 = t * kESplit, s1 = min(s0 + kESplit, n);
-    for (int32_t base = s0; base < s1; base += kEThreads) {
-        const int32_t e = base + (int32_t)threadIdx.x;
-        const bool valid = e < s1;
-        const int32_t cnt = valid ? s.scnt[e] : 1;
-        const uint32_t isf = (valid && cnt == 0) ? 1u : 0u;
-        const uint32_t isu = (valid && cnt != 0) ? 1u : 0u;
-        uint32_t totf, totu;
-        const uint32_t exf = block_exclusive_scan(isf, smem, &totf);
-        const uint32_t exu = block_exclusive_scan(isu, smem + 32, &totu);
-        if (valid) {
-            const uint32_t *r = s.srec + (size_t)e * MP;
-            if (isf) {
-                copy_rec<MP>(s.fdst + (size_t)(of + exf) * MP, r);
-                rank_s[r[M]] = k;
-            } else {
-                const uint32_t slot = ou + exu;
-                copy_rec<MP>(s.udst + (size_t)slot * MP, r);
-                s.rdst[slot] = s.srun[e];
-                s.cdst[slot] = cnt;
-            }
-        }
-        of += totf;
-        ou += totu;
+    const int32_t e0 = t * kESplit, e1 = min(e0 + kESplit, min(n, I.N));
+    uint32_t nf, nu;
+    split_chunk<M>(s, k, e0, e1, ld(&spc[2 * t]), ld(&spc[2 * t + 1]), at<int32_t>(w, L.rank_s),
+                   smem, &nf, &nu);
+}
+
+// Whole split of a short list in one item; writes the level sizes.
+template <int M>
+__device__ void item_split1(const EInst &I, int32_t k, int32_t n, uint32_t *smem) {
+    const ELayout &L = I.L;
+    char *w = I.ws;
+    const LevelLists s = level_lists(w, L, k);
+    n = min(n, I.N);
+    uint32_t of = 0, ou = 0;
+    for (int32_t e0 = 0; e0 < n; e0 += kESplit) {
+        uint32_t nf, nu;
+        split_chunk<M>(s, k, e0, min(e0 + kESplit, n), of, ou, at<int32_t>(w, L.rank_s), smem, &nf,
+                       &nu);
+        of += nf;
+        ou += nu;
+    }
+    if (threadIdx.x == 0) {
+        at<int32_t>(w, L.fsize)[k] = (int32_t)of;
+        at<int32_t>(w, L.usize)[k] = (int32_t)ou;
     }
 }
 
@@ -731,6 +772,7 @@ __device__ void run_item(const EInst &I, int32_t stage, int32_t arg, int32_t n,
         case kSDom: item_dom<M>(I, t, smem); break;
         case kSSplitC: item_splitc(I, arg, n, t, smem); break;
         case kSSplitW: item_splitw<M>(I, arg, n, t, smem); break;
+        case kSSplit1: item_split1<M>(I, arg, n, smem); break;
         case kSPhaseA: item_phase_a<M>(I, arg, p0, p1, t, smem); break;
         case kSOrig: item_orig(I, t); break;
         case kSExt: item_ext<M>(I, t, smem); break;
@@ -925,6 +967,47 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, uint32_t *smem) {
     int32_t stage = ld(&S->stage), arg = ld(&S->arg), n = ld(&S->n);
     int32_t p0 = 0, p1 = 0;
     int64_t items = 0;
+    // level `level` of the peeling starts with a split of a list of `len` entries
+    auto begin_level = [&](int32_t level, int32_t len) {
+        arg = level;
+        n = len;
+        if (n <= kESplitOne) { stage = kSSplit1; items = 1; }
+        else { stage = kSSplitC; items = cdiv(n, kESplit); }
+    };
+    // after the split of level arg: F fronts, U remaining (block-uniform)
+    auto after_split = [&](int32_t F, int32_t U) {
+        if (threadIdx.x == 0) {
+            // a3: the first level whose cumulative size reaches K
+            if (ld(&sc->last_front) < 0 && F > 0) {
+                const int64_t cum = ld(&sc->n_before);
+                if (cum + (int64_t)F >= I.K) {
+                    sc->last_front = arg;
+                    sc->last_front_size = F;
+                    sc->R = I.K - cum;
+                } else {
+                    sc->n_before = cum + F;
+                }
+            }
+            if (F <= 0) atomicOr(&sc->err, (uint32_t)kErrInternal);  // impossible for a partial order
+            if (U == 0) sc->num_fronts = arg + 1;
+        }
+        __syncthreads();
+        if (F <= 0) {
+            stage = kSDone;
+        } else if (U == 0) {
+            stage = kSOrig;
+            items = cdiv(N, kEChunk);
+        } else {
+            const int32_t nJT = (int32_t)cdiv(U, kJT);
+            int32_t IC = 4096 / MP;
+            while (IC > 64 && cdiv(F, IC) * nJT < I.pa_items) IC >>= 1;
+            stage = kSPhaseA;
+            p0 = IC;
+            p1 = nJT;
+            n = U;
+            items = cdiv(F, IC) * nJT;
+        }
+    };
     for (;;) {
         if (ld(&sc->err) != 0) {  // outputs are undefined after a device-side error
             stage = kSDone;
@@ -943,15 +1026,17 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, uint32_t *smem) {
                 break;
             case kSRecs: {
                 stage = kSDom;
-                constexpr int IC = kJT < 8192 / MP ? kJT : 8192 / MP;
                 const int64_t T = cdiv(N, kJT);
-                items = (kJT / IC) * T * (T + 1) / 2;
+                items = T * (T + 1) / 2;
                 break;
             }
             case kSDom:
-                stage = kSSplitC; arg = 0; n = N; items = cdiv(n, kESplit);
-                if (threadIdx.x == 0) { sc->n_before = 0; sc->last_front = -1; }
+                if (threadIdx.x == 0) {
+                    sc->n_before = 0;
+                    sc->last_front = -1;
+                }
                 __syncthreads();
+                begin_level(0, N);
                 break;
             case kSSplitC: {
                 uint32_t *spc = at<uint32_t>(w, L.spc);
@@ -961,42 +1046,17 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, uint32_t *smem) {
                 if (threadIdx.x == 0) {
                     at<int32_t>(w, L.fsize)[arg] = (int32_t)F;
                     at<int32_t>(w, L.usize)[arg] = (int32_t)U;
-                    // a3: the first level whose cumulative size reaches K
-                    if (ld(&sc->last_front) < 0 && F > 0) {
-                        const int64_t cum = ld(&sc->n_before);
-                        if (cum + (int64_t)F >= I.K) {
-                            sc->last_front = arg;
-                            sc->last_front_size = (int32_t)F;
-                            sc->R = I.K - cum;
-                        } else {
-                            sc->n_before = cum + F;
-                        }
-                    }
-                    if (F == 0) atomicOr(&sc->err, (uint32_t)kErrInternal);  // impossible for a partial order
                 }
                 __syncthreads();
-                if (F == 0) { stage = kSDone; break; }
-                stage = kSSplitW; items = m; p0 = (int32_t)F; p1 = (int32_t)U;
+                stage = kSSplitW; items = m;
                 break;
             }
-            case kSSplitW: {
-                const int32_t U = ld(&at<int32_t>(w, L.usize)[arg]);
-                const int32_t F = ld(&at<int32_t>(w, L.fsize)[arg]);
-                if (U == 0) {
-                    if (threadIdx.x == 0) sc->num_fronts = arg + 1;
-                    __syncthreads();
-                    stage = kSOrig; items = cdiv(N, kEChunk);
-                } else {
-                    const int32_t nJT = (int32_t)cdiv(U, kJT);
-                    int32_t IC = 4096 / MP;
-                    while (IC > 64 && cdiv(F, IC) * nJT < I.pa_items) IC >>= 1;
-                    stage = kSPhaseA; p0 = IC; p1 = nJT; n = U;
-                    items = cdiv(F, IC) * nJT;
-                }
+            case kSSplitW:
+            case kSSplit1:
+                after_split(ld(&at<int32_t>(w, L.fsize)[arg]), ld(&at<int32_t>(w, L.usize)[arg]));
                 break;
-            }
             case kSPhaseA:
-                stage = kSSplitC; ++arg; items = cdiv(n, kESplit);
+                begin_level(arg + 1, n);
                 break;
             case kSOrig:
                 stage = kSExt; items = cdiv(N, kEChunk);
@@ -1029,7 +1089,7 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, uint32_t *smem) {
         }
         if (stage == kSDone || items > 0) break;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached the L2
     __syncthreads();
     if (threadIdx.x == 0) {
         if (stage == kSDone) finalize_info(I, sc);
@@ -1039,7 +1099,7 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, uint32_t *smem) {
         S->p0 = p0;
         S->p1 = p1;
         S->done = 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // write every wave's stores back
         __hip_atomic_store(&S->word, stage == kSDone ? 0ull : (uint64_t)items, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
         if (stage == kSDone)
@@ -1051,9 +1111,14 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, uint32_t *smem) {
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void stat_add(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int M>
 __global__ __launch_bounds__(kEThreads) void k_engine(const EInst *__restrict__ inst, EState *st,
-                                                      int32_t b0, int32_t nb, EGlobal *g) {
+                                                      int32_t b0, int32_t nb, EGlobal *g,
+                                                      EStats *stats) {
     __shared__ __attribute__((aligned(16))) uint32_t smem[kESmem];
     __shared__ int32_t s_b, s_item;
     __shared__ uint32_t s_total, s_flag;
@@ -1061,38 +1126,63 @@ __global__ __launch_bounds__(kEThreads) void k_engine(const EInst *__restrict__ 
     int32_t cursor = (int32_t)(blockIdx.x % (uint32_t)nb);
     bool idle = false;
     long long idle_t0 = 0;
+    uint32_t backoff = 1;  // s_sleep units after a search that found nothing
     for (;;) {
+        const long long t0 = stats ? wall_clock64() : 0;
         if (threadIdx.x < kWave) {
             int32_t found = -1;
             uint32_t item = 0, total = 0;
-            for (int32_t base = 0; base < nb; base += kWave) {
-                const int32_t off = base + (int32_t)lane;
-                bool ok = false;
-                if (off < nb) {
-                    int32_t q = cursor + off;
-                    q -= q >= nb ? nb : 0;
-                    const uint64_t wd = ld(&st[b0 + q].word);
-                    ok = (uint32_t)(wd >> 32) < (uint32_t)wd;
+            // the instance this block worked on last comes first: its next
+            // items are usually ready
+            if (lane == 0) {
+                const uint64_t wd = ld(&st[b0 + cursor].word);
+                if ((uint32_t)(wd >> 32) < (uint32_t)wd) {
+                    const uint64_t old = __hip_atomic_fetch_add(&st[b0 + cursor].word, 1ull << 32,
+                                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((uint32_t)(old >> 32) < (uint32_t)old) {
+                        found = cursor;
+                        item = (uint32_t)(old >> 32);
+                        total = (uint32_t)old;
+                    }
                 }
-                uint64_t m = ballot(ok);
-                if (lane == 0) {
-                    while (m) {
-                        const int l = __builtin_ctzll(m);
-                        m &= m - 1;
-                        int32_t q = cursor + base + l;
+            }
+            found = __shfl(found, 0, 64);
+            // then a scan from the next instance on, 4 x 64 progress words in flight
+            const int32_t start = cursor + 1 < nb ? cursor + 1 : 0;
+            for (int32_t base = 0; base < nb && found < 0; base += 4 * kWave) {
+                uint64_t m[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int32_t off = base + r * kWave + (int32_t)lane;
+                    bool ok = false;
+                    if (off < nb) {
+                        int32_t q = start + off;
                         q -= q >= nb ? nb : 0;
-                        const uint64_t old = __hip_atomic_fetch_add(
-                            &st[b0 + q].word, 1ull << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if ((uint32_t)(old >> 32) < (uint32_t)old) {
-                            found = q;
-                            item = (uint32_t)(old >> 32);
-                            total = (uint32_t)old;
-                            break;
+                        const uint64_t wd = ld(&st[b0 + q].word);
+                        ok = (uint32_t)(wd >> 32) < (uint32_t)wd;
+                    }
+                    m[r] = ballot(ok);
+                }
+                if (lane == 0) {
+                    for (int r = 0; r < 4 && found < 0; ++r) {
+                        uint64_t mm = m[r];
+                        while (mm) {
+                            const int l = __builtin_ctzll(mm);
+                            mm &= mm - 1;
+                            int32_t q = start + base + r * kWave + l;
+                            q -= q >= nb ? nb : 0;
+                            const uint64_t old = __hip_atomic_fetch_add(
+                                &st[b0 + q].word, 1ull << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            if ((uint32_t)(old >> 32) < (uint32_t)old) {
+                                found = q;
+                                item = (uint32_t)(old >> 32);
+                                total = (uint32_t)old;
+                                break;
+                            }
                         }
                     }
                 }
                 found = __shfl(found, 0, 64);
-                if (found >= 0) break;
             }
             if (lane == 0) {
                 s_b = found;
@@ -1103,6 +1193,11 @@ __global__ __launch_bounds__(kEThreads) void k_engine(const EInst *__restrict__ 
         }
         __syncthreads();
         const int32_t b = s_b;
+        long long t1 = 0;
+        if (stats && threadIdx.x == 0) {
+            t1 = wall_clock64();
+            stat_add(b < 0 ? &stats->idle : &stats->probe, (unsigned long long)(t1 - t0));
+        }
         if (b < 0) {
             if (threadIdx.x == 0) {
                 uint32_t stop = 0;
@@ -1117,7 +1212,8 @@ __global__ __launch_bounds__(kEThreads) void k_engine(const EInst *__restrict__ 
                         atomicOr(&g->err, (uint32_t)kErrBarrierTimeout);
                         stop = 1;
                     }
-                    __builtin_amdgcn_s_sleep(8);
+                    for (uint32_t q = 0; q < backoff; ++q) __builtin_amdgcn_s_sleep(8);
+                    backoff = backoff < 32u ? 2u * backoff : 32u;
                 }
                 s_flag = stop;
             }
@@ -1126,14 +1222,17 @@ __global__ __launch_bounds__(kEThreads) void k_engine(const EInst *__restrict__ 
             continue;
         }
         idle = false;
+        backoff = 1;
         cursor = b;
         const EInst &I = inst[b0 + b];
         EState *S = st + b0 + b;
-        run_item<M>(I, ld(&S->stage), ld(&S->arg), ld(&S->n), ld(&S->p0), ld(&S->p1), s_item, smem);
-        // every wave publishes its own stores before the item is counted
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const int32_t stage = ld(&S->stage);
+        run_item<M>(I, stage, ld(&S->arg), ld(&S->n), ld(&S->p0), ld(&S->p1), s_item, smem);
+        // every wave's stores reach the L2, then one release writes them back
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const uint32_t d = __hip_atomic_fetch_add(&S->done, 1u, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t last = d + 1 == s_total ? 1u : 0u;
@@ -1141,7 +1240,17 @@ __global__ __launch_bounds__(kEThreads) void k_engine(const EInst *__restrict__ 
             s_flag = last;
         }
         __syncthreads();
-        if (s_flag) advance<M>(I, S, g, smem);
+        long long t2 = 0;
+        if (stats && threadIdx.x == 0) {
+            t2 = wall_clock64();
+            stat_add(&stats->item[stage], (unsigned long long)(t2 - t1));
+            stat_add(&stats->items[stage], 1ull);
+        }
+        if (s_flag) {
+            advance<M>(I, S, g, smem);
+            if (stats && threadIdx.x == 0)
+                stat_add(&stats->epilogue[stage], (unsigned long long)(wall_clock64() - t2));
+        }
         __syncthreads();
     }
 }
@@ -1193,12 +1302,12 @@ hipError_t engine_init(const EInst *inst, EState *st, EGlobal *g, int32_t B, int
 }
 
 hipError_t engine_launch(int M, const EInst *inst, EState *st, int32_t b0, int32_t nb, EGlobal *g,
-                         int grid, hipStream_t s) {
+                         EStats *stats, int grid, hipStream_t s) {
     switch (M) {
 #define NSGA3_CASE(m)                                                                              \
     case m:                                                                                        \
         hipLaunchKernelGGL(k_engine<m>, dim3((unsigned)grid), dim3(kEThreads), 0, s, inst, st, b0, \
-                           nb, g);                                                                 \
+                           nb, g, stats);                                                          \
         break;
         NSGA3_CASE(2) NSGA3_CASE(3) NSGA3_CASE(4) NSGA3_CASE(5) NSGA3_CASE(6) NSGA3_CASE(7)
         NSGA3_CASE(8) NSGA3_CASE(9) NSGA3_CASE(10) NSGA3_CASE(11) NSGA3_CASE(12) NSGA3_CASE(13)

@@ -47,10 +47,12 @@ __device__ __forceinline__ uint32_t tile_one(const uint32_t (&ki)[M], int ipos,
 }
 
 // Streams n earlier records (sorted by position) against the wave's later
-// points.  Records are fetched in groups of kU so the scalar loads overlap.
+// points.  Records are fetched in groups of kU so the scalar loads overlap;
+// RecPtr is a global pointer (scalar loads), a constant-address-space
+// pointer (scalar loads forced) or an LDS pointer.
 // With kCountOut, lane 0 stores the per-record counts to out_row[0..n).
-template <int M, bool kChecked, bool kCountOut>
-__device__ __forceinline__ void tile_rows(const uint32_t *__restrict__ rec, int n,
+template <int M, bool kChecked, bool kCountOut, typename RecPtr>
+__device__ __forceinline__ void tile_rows(RecPtr __restrict__ rec, int n,
                                           const uint32_t (&kj)[kT][M], const int32_t (&run)[kT],
                                           int32_t (&cin)[kT], uint32_t *__restrict__ out_row,
                                           bool lane0) {
@@ -60,7 +62,7 @@ __device__ __forceinline__ void tile_rows(const uint32_t *__restrict__ rec, int 
     for (; ii + kU <= n; ii += kU) {
         uint32_t ki[kU][M];
         int ipos[kU];
-        const uint32_t *g = rec + (size_t)ii * MP;  // one base, constant offsets
+        const RecPtr g = rec + (size_t)ii * MP;  // one base, constant offsets
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
 #pragma unroll
@@ -80,7 +82,7 @@ __device__ __forceinline__ void tile_rows(const uint32_t *__restrict__ rec, int 
         }
     }
     for (; ii < n; ++ii) {
-        const uint32_t *r = rec + (size_t)ii * MP;
+        const RecPtr r = rec + (size_t)ii * MP;
         uint32_t ki[M];
 #pragma unroll
         for (int k = 0; k < M; ++k) ki[k] = r[k];
