@@ -21,7 +21,8 @@ struct nsga3_plan {
     void *ews = nullptr;                 // engine: every instance's workspace
     nsga3::EInst *d_inst = nullptr;      // engine: instance table (sorted by M)
     nsga3::EState *d_state = nullptr;
-    nsga3::EGlobal *d_glob = nullptr;    // one per objective count
+    nsga3::EGlobal *d_glob = nullptr;    // two per objective count (before / after the counts)
+    int2 *d_map = nullptr;               // (instance, item) of every dominance-count block
     nsga3::EStats *d_stats = nullptr;    // engine diagnostics (plans created while profiling)
     int clock_khz = 0;
     std::vector<void *> ws;
@@ -514,6 +515,7 @@ static void plan_free(nsga3_plan *pl) {
     if (pl->d_inst) (void)hipFree(pl->d_inst);
     if (pl->d_state) (void)hipFree(pl->d_state);
     if (pl->d_glob) (void)hipFree(pl->d_glob);
+    if (pl->d_map) (void)hipFree(pl->d_map);
     if (pl->d_stats) (void)hipFree(pl->d_stats);
     delete pl;
 }
@@ -544,7 +546,7 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
         (void)hipGetLastError();
         return NSGA3_E_NOMEM;
     }
-    int pa_items = 32;
+    int pa_items = 8;
     if (const char *e = getenv("NSGA3_ENGINE_PA_ITEMS")) {
         const int v = atoi(e);
         if (v >= 1 && v <= 1 << 20) pa_items = v;
@@ -573,10 +575,25 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
         cls.back().second++;
     }
     const int nclass = (int)cls.size();
-    if (hipMalloc((void **)&pl->d_glob, sizeof(EGlobal) * (size_t)nclass) != hipSuccess) {
+    // dominance-count blocks of every class: (instance, item)
+    std::vector<int2> map;
+    std::vector<int64_t> map_off(nclass + 1, 0);
+    for (int c = 0; c < nclass; ++c) {
+        map_off[c] = (int64_t)map.size();
+        for (int32_t q = cls[c].first; q < cls[c].first + cls[c].second; ++q) {
+            const int64_t items = engine_dom_items(inst[q].N);
+            for (int64_t t = 0; t < items; ++t) map.push_back(make_int2(q, (int)t));
+        }
+    }
+    map_off[nclass] = (int64_t)map.size();
+    if (hipMalloc((void **)&pl->d_glob, sizeof(EGlobal) * (size_t)(2 * nclass)) != hipSuccess ||
+        hipMalloc((void **)&pl->d_map, sizeof(int2) * (map.size() ? map.size() : 1)) != hipSuccess) {
         (void)hipGetLastError();
         return NSGA3_E_NOMEM;
     }
+    if (!map.empty() &&
+        hipMemcpy(pl->d_map, map.data(), sizeof(int2) * map.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return NSGA3_E_HIP;
     if (hipMemcpy(pl->d_inst, inst.data(), sizeof(EInst) * (size_t)B, hipMemcpyHostToDevice) !=
         hipSuccess)
         return NSGA3_E_HIP;
@@ -603,21 +620,34 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
     if (e != hipSuccess) return NSGA3_E_HIP;
     pl->branches = nclass;
     e = hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = engine_init(pl->d_inst, pl->d_state, pl->d_glob, B, nclass, pl->cap);
+    if (e == hipSuccess) e = engine_init(pl->d_inst, pl->d_state, pl->d_glob, B, 2 * nclass, pl->cap);
     if (e == hipSuccess) e = hipEventRecord(pl->events[nclass], pl->cap);
     for (int c = 0; c < nclass && e == hipSuccess; ++c) {
         const int M = inst[cls[c].first].M;
-        int bpc = engine_blocks_per_cu(M);
+        // one resident worker per CU and class: idle workers that poll for
+        // items slow the working ones down more than extra workers help
+        const int occ = engine_blocks_per_cu(M);
+        int bpc = 1;
         if (const char *ev = getenv("NSGA3_ENGINE_BLOCKS_PER_CU")) {
             const int v = atoi(ev);
-            if (v >= 1 && v < bpc) bpc = v;
+            if (v >= 1 && v <= occ) bpc = v;
         }
-        if (bpc < 1) bpc = 1;
         const int grid = ctx->num_cus * bpc;
-        e = hipStreamWaitEvent(pl->streams[c], pl->events[nclass], 0);
+        const int32_t b0 = cls[c].first, nb = cls[c].second;
+        hipStream_t bs = pl->streams[c];
+        e = hipStreamWaitEvent(bs, pl->events[nclass], 0);
+        // keys, presort and records; parked before the dominance counts
         if (e == hipSuccess)
-            e = engine_launch(M, pl->d_inst, pl->d_state, cls[c].first, cls[c].second,
-                              pl->d_glob + c, pl->d_stats, grid, pl->streams[c]);
+            e = engine_launch(M, pl->d_inst, pl->d_state, b0, nb, pl->d_glob + c, pl->d_stats, kSDom,
+                              grid, bs);
+        if (e == hipSuccess)
+            e = engine_dom_launch(M, pl->d_inst, pl->d_state, pl->d_map + map_off[c],
+                                  map_off[c + 1] - map_off[c], bs);
+        if (e == hipSuccess) e = engine_resume(pl->d_inst, pl->d_state, b0, nb, pl->d_glob + nclass + c, bs);
+        // peeling, normalisation, association, niching, output
+        if (e == hipSuccess)
+            e = engine_launch(M, pl->d_inst, pl->d_state, b0, nb, pl->d_glob + nclass + c, pl->d_stats,
+                              kSDone, grid, bs);
         if (e == hipSuccess) e = hipEventRecord(pl->events[c], pl->streams[c]);
         if (e == hipSuccess) e = hipStreamWaitEvent(pl->cap, pl->events[c], 0);
     }

@@ -154,8 +154,23 @@ struct EStats {
 // Launches (engine.hip).  Instances [b0, b0 + nb) of `inst` must share M.
 hipError_t engine_init(const EInst *inst, EState *st, EGlobal *g, int32_t B, int32_t nclass,
                        hipStream_t s);
+// Runs instances [b0, b0 + nb) until each is done or reaches stop_stage
+// (then parked with no items).
 hipError_t engine_launch(int M, const EInst *inst, EState *st, int32_t b0, int32_t nb, EGlobal *g,
-                         EStats *stats, int grid, hipStream_t s);
+                         EStats *stats, int32_t stop_stage, int grid, hipStream_t s);
+// Dominance counts of every parked instance as one ordinary launch; map[q]
+// = (instance, item) of block q, nblocks blocks.
+hipError_t engine_dom_launch(int M, const EInst *inst, const EState *st, const int2 *map,
+                             int64_t nblocks, hipStream_t s);
+// Moves parked instances [b0, b0 + nb) to the first peeling level; instances
+// already done count as finished in g.
+hipError_t engine_resume(const EInst *inst, EState *st, int32_t b0, int32_t nb, EGlobal *g,
+                         hipStream_t s);
+// Number of dominance items of an instance of N points.
+inline int64_t engine_dom_items(int64_t N) {
+    const int64_t T = cdiv(N, 1024);
+    return T * (T + 1) / 2;
+}
 int engine_blocks_per_cu(int M);
 
 }  // namespace nsga3

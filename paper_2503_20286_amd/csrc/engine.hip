@@ -958,7 +958,7 @@ __device__ void finalize_info(const EInst &I, EScal *sc) {
 // Runs the epilogue of the stage that just completed and publishes the next
 // stage with at least one item (or marks the instance done).
 template <int M>
-__device__ void advance(const EInst &I, EState *S, EGlobal *g, uint32_t *smem) {
+__device__ void advance(const EInst &I, EState *S, EGlobal *g, int32_t stop_stage, uint32_t *smem) {
     constexpr int MP = rec_stride(M);
     char *w = I.ws;
     const ELayout &L = I.L;
@@ -1092,6 +1092,7 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, uint32_t *smem) {
     __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached the L2
     __syncthreads();
     if (threadIdx.x == 0) {
+        const bool leave = stage == kSDone || stage == stop_stage;  // done, or parked
         if (stage == kSDone) finalize_info(I, sc);
         S->stage = stage;
         S->arg = arg;
@@ -1100,9 +1101,9 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, uint32_t *smem) {
         S->p1 = p1;
         S->done = 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // write every wave's stores back
-        __hip_atomic_store(&S->word, stage == kSDone ? 0ull : (uint64_t)items, __ATOMIC_RELAXED,
+        __hip_atomic_store(&S->word, leave ? 0ull : (uint64_t)items, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        if (stage == kSDone)
+        if (leave)
             __hip_atomic_fetch_add(&g->finished, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
@@ -1118,7 +1119,7 @@ __device__ __forceinline__ void stat_add(unsigned long long *p, unsigned long lo
 template <int M>
 __global__ __launch_bounds__(kEThreads) void k_engine(const EInst *__restrict__ inst, EState *st,
                                                       int32_t b0, int32_t nb, EGlobal *g,
-                                                      EStats *stats) {
+                                                      EStats *stats, int32_t stop_stage) {
     __shared__ __attribute__((aligned(16))) uint32_t smem[kESmem];
     __shared__ int32_t s_b, s_item;
     __shared__ uint32_t s_total, s_flag;
@@ -1247,7 +1248,7 @@ __global__ __launch_bounds__(kEThreads) void k_engine(const EInst *__restrict__ 
             stat_add(&stats->items[stage], 1ull);
         }
         if (s_flag) {
-            advance<M>(I, S, g, smem);
+            advance<M>(I, S, g, stop_stage, smem);
             if (stats && threadIdx.x == 0)
                 stat_add(&stats->epilogue[stage], (unsigned long long)(wall_clock64() - t2));
         }
@@ -1291,7 +1292,75 @@ __global__ void k_engine_init(const EInst *__restrict__ inst, EState *st, EGloba
     S.word = (uint64_t)(cdiv(I.N, kEChunk) + cdiv(I.H, kEThreads));
 }
 
+// Dominance counts of parked instances, one (instance, item) per block.  The
+// instance tables and records were written by an earlier launch, so plain
+// scalar loads are safe here.
+template <int M>
+__global__ __launch_bounds__(kEThreads) void k_engine_dom(const EInst *__restrict__ inst,
+                                                          const EState *__restrict__ st,
+                                                          const int2 *__restrict__ map) {
+    __shared__ __attribute__((aligned(16))) uint32_t smem[kWaves * kJT];
+    const int2 e = map[blockIdx.x];
+    if (st[e.x].stage != kSDom) return;  // finished early (device-side error)
+    item_dom<M>(inst[e.x], e.y, smem);
+}
+
+// Parked instances -> first peeling level (the level-0 split of every point).
+__global__ void k_engine_resume(const EInst *__restrict__ inst, EState *st, int32_t b0, int32_t nb,
+                                EGlobal *g) {
+    const int32_t q = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (q >= nb) return;  // g was cleared by the reset kernel
+    const int32_t b = b0 + q;
+    const EInst &I = inst[b];
+    EState &S = st[b];
+    EScal *sc = at<EScal>(I.ws, I.L.scal);
+    if (S.stage != kSDom || sc->err != 0) {  // already done: counts as finished
+        S.stage = kSDone;
+        S.word = 0ull;
+        atomicAdd(&g->finished, 1u);
+        return;
+    }
+    sc->n_before = 0;
+    sc->last_front = -1;
+    S.arg = 0;
+    S.n = I.N;
+    S.p0 = S.p1 = 0;
+    S.done = 0;
+    if (I.N <= kESplitOne) {
+        S.stage = kSSplit1;
+        S.word = 1ull;
+    } else {
+        S.stage = kSSplitC;
+        S.word = (uint64_t)cdiv(I.N, kESplit);
+    }
+}
+
 }  // namespace
+
+hipError_t engine_dom_launch(int M, const EInst *inst, const EState *st, const int2 *map,
+                             int64_t nblocks, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    switch (M) {
+#define NSGA3_CASE(m)                                                                              \
+    case m:                                                                                        \
+        hipLaunchKernelGGL(k_engine_dom<m>, dim3((unsigned)nblocks), dim3(kEThreads), 0, s, inst, \
+                           st, map);                                                               \
+        break;
+        NSGA3_CASE(2) NSGA3_CASE(3) NSGA3_CASE(4) NSGA3_CASE(5) NSGA3_CASE(6) NSGA3_CASE(7)
+        NSGA3_CASE(8) NSGA3_CASE(9) NSGA3_CASE(10) NSGA3_CASE(11) NSGA3_CASE(12) NSGA3_CASE(13)
+        NSGA3_CASE(14) NSGA3_CASE(15) NSGA3_CASE(16)
+#undef NSGA3_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t engine_resume(const EInst *inst, EState *st, int32_t b0, int32_t nb, EGlobal *g,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_engine_resume, dim3((unsigned)cdiv(nb, 64)), dim3(64), 0, s, inst, st, b0,
+                       nb, g);
+    return hipGetLastError();
+}
 
 hipError_t engine_init(const EInst *inst, EState *st, EGlobal *g, int32_t B, int32_t nclass,
                        hipStream_t s) {
@@ -1302,12 +1371,12 @@ hipError_t engine_init(const EInst *inst, EState *st, EGlobal *g, int32_t B, int
 }
 
 hipError_t engine_launch(int M, const EInst *inst, EState *st, int32_t b0, int32_t nb, EGlobal *g,
-                         EStats *stats, int grid, hipStream_t s) {
+                         EStats *stats, int32_t stop_stage, int grid, hipStream_t s) {
     switch (M) {
 #define NSGA3_CASE(m)                                                                              \
     case m:                                                                                        \
         hipLaunchKernelGGL(k_engine<m>, dim3((unsigned)grid), dim3(kEThreads), 0, s, inst, st, b0, \
-                           nb, g, stats);                                                          \
+                           nb, g, stats, stop_stage);                                              \
         break;
         NSGA3_CASE(2) NSGA3_CASE(3) NSGA3_CASE(4) NSGA3_CASE(5) NSGA3_CASE(6) NSGA3_CASE(7)
         NSGA3_CASE(8) NSGA3_CASE(9) NSGA3_CASE(10) NSGA3_CASE(11) NSGA3_CASE(12) NSGA3_CASE(13)
