@@ -54,8 +54,8 @@ def parse():
     ap.add_argument("--plan-compare", action="store_true",
                     help="also time the batch as a graph of single selections")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="only run a plain device copy of this many MiB (three times), to scale "
-                         "the FETCH_SIZE / WRITE_SIZE counters")
+                    help="first run a plain device copy of this many MiB (three times), whose "
+                         "FETCH_SIZE / WRITE_SIZE counters scale those of the library's kernels")
     return ap.parse_args()
 
 
@@ -152,10 +152,10 @@ def batched(args):
     import workloads
     ws = workloads.make_batch(args.batch)
     probs = [(torch.from_numpy(w.objs).cuda(), torch.from_numpy(w.refs).cuda(), w.K) for w in ws]
-    ctx = nsga3.Context(0)
+    ctx = nsga3.Context(0, autotune=True)
     ctx.reserve(max(w.N for w in ws), 5, 210)
     t0 = time.perf_counter()
-    plan = nsga3.Plan(probs, ctx=ctx)
+    plan = nsga3.Plan(probs, ctx=ctx)  # times candidate work-item shapes per (M, N range)
     t_create = time.perf_counter() - t0
     stream = torch.cuda.current_stream()
     for _ in range(max(args.warmup, 1)):
@@ -186,8 +186,22 @@ def batched(args):
                for a, b in zip(plan.results, outs))
     info = plan.info()
     plan.close()
+    tuned = ctx.tuned_shapes()
     n_pts = sum(w.N for w in ws)
     extra = {}
+    # the same batch with the fixed default shapes, for comparison
+    dctx = nsga3.Context(0)
+    pd = nsga3.Plan(probs, ctx=dctx)
+    pd.launch(stream)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        pd.launch(stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    extra["default_shapes_ms_per_launch"] = start.elapsed_time(stop) / steps
+    pd.close()
+    dctx.close()
     if args.engine_stats:
         pctx = nsga3.Context(0)
         pctx.profile(True)
@@ -226,7 +240,8 @@ def batched(args):
         "total_points": n_pts,
         "graph_branches": info["branches"],
         "graph_nodes": info["nodes"],
-        "plan_create_s": t_create,
+        "plan_create_s_with_autotune": t_create,
+        "tuned_shapes": tuned,
         "single_calls_ms": ms_single,
         "single_calls_sel_per_s": args.batch / (ms_single / 1e3),
         "speedup_vs_single_calls": ms_single / ms_graph,
@@ -258,8 +273,7 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"calibrate_copy_bytes": n * 4}), flush=True)
-        return
+        del src, dst
     nsga3.load()
     w = workloads.make(args.workload)
     dev = torch.device("cuda:0")

@@ -59,7 +59,10 @@ typedef enum {
 
 typedef struct {
     nsga3_assoc_mode assoc;       /* default NSGA3_ASSOC_FP32 */
-    int32_t reserved0;
+    int32_t autotune;             /* 1: nsga3_plan_create times candidate work-item shapes per
+                                     (M, N range) on the plan's own problems and keeps the
+                                     fastest (cached in the context); 0: fixed defaults.
+                                     Results never depend on the choice. */
     size_t max_workspace_bytes;   /* 0 = no cap */
 } nsga3_options;
 
@@ -179,13 +182,21 @@ nsga3_status nsga3_plan_info(const nsga3_plan *plan, int32_t *branches, int64_t 
  * the plan is still running.  NULL is ignored. */
 void nsga3_plan_destroy(nsga3_plan *plan);
 
+/* Work-item shapes the autotuner chose so far in this context, 5 int32 per
+ * entry: M, N range (0: N < 2048, 1: < 8192, 2: < 32768, 3: larger), phase-A
+ * items per level, longest remaining list peeled in one item (0: never), and
+ * largest front for that.  Writes at most `cap` entries to out (host) and the
+ * number of entries to *count (host). */
+nsga3_status nsga3_tuned_shapes(const nsga3_ctx *ctx, int32_t *out, int32_t cap, int32_t *count);
+
 /* Engine stages (index into the arrays of nsga3_plan_stage_times):
  *   0 keys and references, 1 radix histogram, 2 radix scatter, 3 sorted records,
  *   4 dominance counts, 5 split counts, 6 split writes, 7 peeling decrements,
  *   8 outputs in original order, 9 extreme points, 10 association,
  *   11 bucket scatter, 12 niche picks, 13 compaction counts, 14 compaction
- *   writes, 15 short-list split in one item, 16 done. */
-#define NSGA3_PLAN_STAGES 17
+ *   writes, 15 short-list split in one item, 16 remaining levels in one item,
+ *   17 done. */
+#define NSGA3_PLAN_STAGES 18
 
 /* Diagnostics of a plan created while profiling was enabled: per stage, the
  * block-milliseconds spent inside its work items and its epilogues, and the

@@ -38,14 +38,14 @@ class NativeError(RuntimeError):
 
 
 class _Options(ctypes.Structure):
-    _fields_ = [("assoc", ctypes.c_int), ("reserved0", ctypes.c_int32),
+    _fields_ = [("assoc", ctypes.c_int), ("autotune", ctypes.c_int32),
                 ("max_workspace_bytes", ctypes.c_size_t)]
 
 
 PLAN_STAGES = ("keys_refs", "radix_hist", "radix_scatter", "records", "dominance",
                "split_count", "split_write", "peel_decrements", "orig_order", "extremes",
                "association", "bucket_scatter", "niche_picks", "compact_count", "compact_write",
-               "split_one", "done")
+               "split_one", "peel_tail", "done")
 
 
 class _Problem(ctypes.Structure):
@@ -103,6 +103,8 @@ def load():
                                              ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_double)]
         L.nsga3_plan_stage_times.restype = ctypes.c_int
+        L.nsga3_tuned_shapes.argtypes = [P, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
+        L.nsga3_tuned_shapes.restype = ctypes.c_int
         L.nsga3_plan_destroy.argtypes = [P]
         L.nsga3_plan_destroy.restype = None
         L.nsga3_version.argtypes = []
@@ -139,9 +141,10 @@ def exported_symbols():
 class Context:
     """Owns an nsga3_ctx (device workspace) on one HIP device."""
 
-    def __init__(self, device: int = 0, assoc: int = ASSOC_FP32, max_workspace_bytes: int = 0):
+    def __init__(self, device: int = 0, assoc: int = ASSOC_FP32, max_workspace_bytes: int = 0,
+                 autotune: bool = False):
         self._lib = load()
-        opt = _Options(assoc, 0, max_workspace_bytes)
+        opt = _Options(assoc, 1 if autotune else 0, max_workspace_bytes)
         h = ctypes.c_void_p()
         rc = self._lib.nsga3_create(ctypes.byref(h), int(device), ctypes.byref(opt))
         if rc != 0:
@@ -163,6 +166,19 @@ class Context:
         rc = self._lib.nsga3_profile(self._h, 1 if enable else 0)
         if rc != 0:
             raise NativeError("nsga3_profile", rc, self._lib)
+
+    def tuned_shapes(self):
+        """Autotuned engine shapes: list of dicts (M, n_range, pa_items, tail_max, tail_front)."""
+        cnt = ctypes.c_int32()
+        rc = self._lib.nsga3_tuned_shapes(self._h, None, 0, ctypes.byref(cnt))
+        if rc != 0:
+            raise NativeError("nsga3_tuned_shapes", rc, self._lib)
+        buf = (ctypes.c_int32 * (5 * max(cnt.value, 1)))()
+        rc = self._lib.nsga3_tuned_shapes(self._h, buf, cnt.value, ctypes.byref(cnt))
+        if rc != 0:
+            raise NativeError("nsga3_tuned_shapes", rc, self._lib)
+        keys = ("M", "n_range", "pa_items", "tail_max", "tail_front")
+        return [dict(zip(keys, buf[5 * q:5 * q + 5])) for q in range(cnt.value)]
 
     def phase_times(self):
         """(per-phase summed milliseconds, number of calls) since profiling was enabled."""

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -33,9 +34,16 @@ struct nsga3_plan {
     hipGraphExec_t exec = nullptr;
 };
 
+struct EngineShape {        // per-instance work-item shape of the batched engine
+    int32_t pa_items;
+    int32_t tail_max;
+    int32_t tail_front;
+};
+
 struct nsga3_ctx {
     int device;
     nsga3_options opt;
+    std::map<std::pair<int, int>, EngineShape> tuned;  // (M, N range) -> fastest shape
     int num_cus;
     int peel_bpc[17];
     void *ws;
@@ -371,7 +379,7 @@ nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt)
     if (!c) return NSGA3_E_NOMEM;
     c->device = device;
     c->opt.assoc = NSGA3_ASSOC_FP32;
-    c->opt.reserved0 = 0;
+    c->opt.autotune = 0;
     c->opt.max_workspace_bytes = 0;
     if (opt) c->opt = *opt;
     if (c->opt.assoc != NSGA3_ASSOC_FP32 && c->opt.assoc != NSGA3_ASSOC_BF16) {
@@ -520,6 +528,87 @@ static void plan_free(nsga3_plan *pl) {
     delete pl;
 }
 
+// N ranges the tuner tells apart.
+static int n_range(int64_t N) { return N < 2048 ? 0 : N < 8192 ? 1 : N < 32768 ? 2 : 3; }
+
+static const EngineShape kShapeDefault = {8, nsga3::kETailDefault, nsga3::kETailFrontDefault};
+static const EngineShape kShapeCandidates[] = {
+    {8, 0, 0},        {8, 8192, 256},    {8, 8192, 1024},   {8, 32768, 256},
+    {8, 32768, 1024}, {32, 8192, 1024},  {32, 0, 0},
+};
+
+// Times the whole engine pipeline on one group of instances (all of one M),
+// eagerly on `s`, for every candidate shape; returns the fastest.  The group's
+// instances use their own workspaces; their outputs are overwritten (the plan
+// launches overwrite them again).
+static nsga3_status tune_group(nsga3_ctx *ctx, const std::vector<nsga3::EInst> &group, int grid,
+                               hipStream_t s, EngineShape *best) {
+    using namespace nsga3;
+    const int32_t nb = (int32_t)group.size();
+    std::vector<int2> map;
+    for (int32_t q = 0; q < nb; ++q)
+        for (int64_t t = 0; t < engine_dom_items(group[q].N); ++t) map.push_back(make_int2(q, (int)t));
+    EInst *d_inst = nullptr;
+    EState *d_state = nullptr;
+    EGlobal *d_glob = nullptr;
+    int2 *d_map = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    nsga3_status st = NSGA3_OK;
+    if (hipMalloc((void **)&d_inst, sizeof(EInst) * nb) != hipSuccess ||
+        hipMalloc((void **)&d_state, sizeof(EState) * nb) != hipSuccess ||
+        hipMalloc((void **)&d_glob, sizeof(EGlobal) * 2) != hipSuccess ||
+        hipMalloc((void **)&d_map, sizeof(int2) * (map.empty() ? 1 : map.size())) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipGetLastError();
+        st = NSGA3_E_NOMEM;
+    }
+    if (st == NSGA3_OK && !map.empty() &&
+        hipMemcpy(d_map, map.data(), sizeof(int2) * map.size(), hipMemcpyHostToDevice) != hipSuccess)
+        st = NSGA3_E_HIP;
+    const int M = group[0].M;
+    float best_ms = -1.0f;
+    std::vector<EInst> cand(group);
+    for (const EngineShape &sh : kShapeCandidates) {
+        if (st != NSGA3_OK) break;
+        for (EInst &e : cand) {
+            e.pa_items = sh.pa_items;
+            e.tail_max = sh.tail_max;
+            e.tail_front = sh.tail_front;
+        }
+        if (hipMemcpy(d_inst, cand.data(), sizeof(EInst) * nb, hipMemcpyHostToDevice) != hipSuccess) {
+            st = NSGA3_E_HIP;
+            break;
+        }
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && st == NSGA3_OK; ++rep) {  // the second run is timed
+            hipError_t e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = engine_init(d_inst, d_state, d_glob, nb, 2, s);
+            if (e == hipSuccess) e = engine_launch(M, d_inst, d_state, 0, nb, d_glob, nullptr, kSDom, grid, s);
+            if (e == hipSuccess) e = engine_dom_launch(M, d_inst, d_state, d_map, (int64_t)map.size(), s);
+            if (e == hipSuccess) e = engine_resume(d_inst, d_state, 0, nb, d_glob + 1, s);
+            if (e == hipSuccess) e = engine_launch(M, d_inst, d_state, 0, nb, d_glob + 1, nullptr, kSDone, grid, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                st = NSGA3_E_HIP;
+            }
+        }
+        if (st == NSGA3_OK && (best_ms < 0.0f || ms < best_ms)) {
+            best_ms = ms;
+            *best = sh;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (d_inst) (void)hipFree(d_inst);
+    if (d_state) (void)hipFree(d_state);
+    if (d_glob) (void)hipFree(d_glob);
+    if (d_map) (void)hipFree(d_map);
+    return st;
+}
+
 // Batched plan through the engine: instances sorted by M, one persistent
 // engine launch per objective count (on forked streams), all captured with
 // the reset kernel into one graph.
@@ -546,10 +635,18 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
         (void)hipGetLastError();
         return NSGA3_E_NOMEM;
     }
-    int pa_items = 8;
+    EngineShape base = kShapeDefault;
     if (const char *e = getenv("NSGA3_ENGINE_PA_ITEMS")) {
         const int v = atoi(e);
-        if (v >= 1 && v <= 1 << 20) pa_items = v;
+        if (v >= 1 && v <= 1 << 20) base.pa_items = v;
+    }
+    if (const char *e = getenv("NSGA3_ENGINE_TAIL_MAX")) {
+        const int v = atoi(e);
+        if (v >= 0) base.tail_max = v;
+    }
+    if (const char *e = getenv("NSGA3_ENGINE_TAIL_FRONT")) {
+        const int v = atoi(e);
+        if (v >= 0) base.tail_front = v;
     }
     std::vector<std::pair<int32_t, int32_t>> cls;  // (first instance, count) per M
     for (int32_t q = 0; q < B; ++q) {
@@ -569,7 +666,9 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
         e.N = (int32_t)p.N;
         e.M = p.M;
         e.H = p.H;
-        e.pa_items = pa_items;
+        e.pa_items = base.pa_items;
+        e.tail_max = base.tail_max;
+        e.tail_front = base.tail_front;
         e.L = elayout(p.N, p.M, p.H);
         if (q == 0 || p.M != probs[order[q - 1]].M) cls.push_back({q, 0});
         cls.back().second++;
@@ -594,6 +693,31 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
     if (!map.empty() &&
         hipMemcpy(pl->d_map, map.data(), sizeof(int2) * map.size(), hipMemcpyHostToDevice) != hipSuccess)
         return NSGA3_E_HIP;
+    if (ctx->opt.autotune) {
+        // shapes per (M, N range): tune the groups the context has not seen
+        std::map<std::pair<int, int>, std::vector<int32_t>> groups;
+        for (int32_t q = 0; q < B; ++q) groups[{inst[q].M, n_range(inst[q].N)}].push_back(q);
+        hipStream_t ts = nullptr;
+        if (hipStreamCreateWithFlags(&ts, hipStreamNonBlocking) != hipSuccess) return NSGA3_E_HIP;
+        nsga3_status st = NSGA3_OK;
+        for (auto &kv : groups) {
+            if (ctx->tuned.count(kv.first)) continue;
+            std::vector<EInst> g;
+            for (int32_t q : kv.second) g.push_back(inst[q]);
+            EngineShape best = kShapeDefault;
+            st = tune_group(ctx, g, ctx->num_cus, ts, &best);
+            if (st != NSGA3_OK) break;
+            ctx->tuned[kv.first] = best;
+        }
+        (void)hipStreamDestroy(ts);
+        if (st != NSGA3_OK) return st;
+        for (int32_t q = 0; q < B; ++q) {
+            const EngineShape &sh = ctx->tuned[{inst[q].M, n_range(inst[q].N)}];
+            inst[q].pa_items = sh.pa_items;
+            inst[q].tail_max = sh.tail_max;
+            inst[q].tail_front = sh.tail_front;
+        }
+    }
     if (hipMemcpy(pl->d_inst, inst.data(), sizeof(EInst) * (size_t)B, hipMemcpyHostToDevice) !=
         hipSuccess)
         return NSGA3_E_HIP;
@@ -612,44 +736,60 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
         e = hipStreamCreateWithFlags(&bs, hipStreamNonBlocking);
         if (e == hipSuccess) pl->streams.push_back(bs);
     }
-    for (int c = 0; c <= nclass && e == hipSuccess; ++c) {
+    // events: fork, one per class for each of the two engine phases
+    for (int c = 0; c < 2 * nclass + 2 && e == hipSuccess; ++c) {
         hipEvent_t ev;
         e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e == hipSuccess) pl->events.push_back(ev);
     }
     if (e != hipSuccess) return NSGA3_E_HIP;
     pl->branches = nclass;
-    e = hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = engine_init(pl->d_inst, pl->d_state, pl->d_glob, B, 2 * nclass, pl->cap);
-    if (e == hipSuccess) e = hipEventRecord(pl->events[nclass], pl->cap);
-    for (int c = 0; c < nclass && e == hipSuccess; ++c) {
-        const int M = inst[cls[c].first].M;
+    std::vector<int> grid(nclass);
+    for (int c = 0; c < nclass; ++c) {
         // one resident worker per CU and class: idle workers that poll for
         // items slow the working ones down more than extra workers help
+        const int M = inst[cls[c].first].M;
         const int occ = engine_blocks_per_cu(M);
         int bpc = 1;
         if (const char *ev = getenv("NSGA3_ENGINE_BLOCKS_PER_CU")) {
             const int v = atoi(ev);
             if (v >= 1 && v <= occ) bpc = v;
         }
-        const int grid = ctx->num_cus * bpc;
-        const int32_t b0 = cls[c].first, nb = cls[c].second;
+        grid[c] = ctx->num_cus * bpc;
+    }
+    hipEvent_t *ev = pl->events.data();
+    // phase 1 (branch per class): keys, presort, records; parked before the counts
+    e = hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = engine_init(pl->d_inst, pl->d_state, pl->d_glob, B, 2 * nclass, pl->cap);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * nclass], pl->cap);
+    for (int c = 0; c < nclass && e == hipSuccess; ++c) {
+        const int M = inst[cls[c].first].M;
+        e = hipStreamWaitEvent(pl->streams[c], ev[2 * nclass], 0);
+        if (e == hipSuccess)
+            e = engine_launch(M, pl->d_inst, pl->d_state, cls[c].first, cls[c].second, pl->d_glob + c,
+                              pl->d_stats, kSDom, grid[c], pl->streams[c]);
+        if (e == hipSuccess) e = hipEventRecord(ev[c], pl->streams[c]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(pl->cap, ev[c], 0);
+    }
+    // phase 2: the dominance counts of every instance, with no engine running
+    // (the engines' cache invalidations would keep these launches' data cold)
+    for (int c = 0; c < nclass && e == hipSuccess; ++c)
+        e = engine_dom_launch(inst[cls[c].first].M, pl->d_inst, pl->d_state, pl->d_map + map_off[c],
+                              map_off[c + 1] - map_off[c], pl->cap);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * nclass + 1], pl->cap);
+    // phase 3 (branch per class): peeling, normalisation, association, niching, output
+    for (int c = 0; c < nclass && e == hipSuccess; ++c) {
+        const int M = inst[cls[c].first].M;
         hipStream_t bs = pl->streams[c];
-        e = hipStreamWaitEvent(bs, pl->events[nclass], 0);
-        // keys, presort and records; parked before the dominance counts
+        e = hipStreamWaitEvent(bs, ev[2 * nclass + 1], 0);
         if (e == hipSuccess)
-            e = engine_launch(M, pl->d_inst, pl->d_state, b0, nb, pl->d_glob + c, pl->d_stats, kSDom,
-                              grid, bs);
+            e = engine_resume(pl->d_inst, pl->d_state, cls[c].first, cls[c].second,
+                              pl->d_glob + nclass + c, bs);
         if (e == hipSuccess)
-            e = engine_dom_launch(M, pl->d_inst, pl->d_state, pl->d_map + map_off[c],
-                                  map_off[c + 1] - map_off[c], bs);
-        if (e == hipSuccess) e = engine_resume(pl->d_inst, pl->d_state, b0, nb, pl->d_glob + nclass + c, bs);
-        // peeling, normalisation, association, niching, output
-        if (e == hipSuccess)
-            e = engine_launch(M, pl->d_inst, pl->d_state, b0, nb, pl->d_glob + nclass + c, pl->d_stats,
-                              kSDone, grid, bs);
-        if (e == hipSuccess) e = hipEventRecord(pl->events[c], pl->streams[c]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(pl->cap, pl->events[c], 0);
+            e = engine_launch(M, pl->d_inst, pl->d_state, cls[c].first, cls[c].second,
+                              pl->d_glob + nclass + c, pl->d_stats, kSDone, grid[c], bs);
+        if (e == hipSuccess) e = hipEventRecord(ev[nclass + c], bs);
+        if (e == hipSuccess) e = hipStreamWaitEvent(pl->cap, ev[nclass + c], 0);
     }
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(pl->cap, &graph);
@@ -792,6 +932,24 @@ nsga3_status nsga3_plan_info(const nsga3_plan *plan, int32_t *branches, int64_t 
     if (!plan) return NSGA3_E_INVALID;
     if (branches) *branches = plan->branches;
     if (nodes) *nodes = plan->nodes;
+    return NSGA3_OK;
+}
+
+nsga3_status nsga3_tuned_shapes(const nsga3_ctx *ctx, int32_t *out, int32_t cap, int32_t *count) {
+    if (!ctx || !count || cap < 0 || (cap > 0 && !out)) return NSGA3_E_INVALID;
+    int32_t n = 0;
+    for (const auto &kv : ctx->tuned) {
+        if (n < cap) {
+            int32_t *r = out + 5 * n;
+            r[0] = kv.first.first;
+            r[1] = kv.first.second;
+            r[2] = kv.second.pa_items;
+            r[3] = kv.second.tail_max;
+            r[4] = kv.second.tail_front;
+        }
+        ++n;
+    }
+    *count = n;
     return NSGA3_OK;
 }
 

@@ -142,9 +142,14 @@ __device__ __forceinline__ void load_points(const uint32_t *__restrict__ jrec,
 }
 
 // ---------------------------------------------------------------------------
-// In-degrees over all points (static grid: x = block chunk, y = point tile;
-// chunks entirely after the tile's last run start exit at once).
+// In-degrees over all points.  Grid: x = group of kTilesPerItem point tiles,
+// y = block chunk, so that neighbouring work-groups share the chunk staged in
+// LDS (read from L2 once per XCD instead of once per tile); each work-group
+// reuses its chunk for kTilesPerItem tiles.  Chunks entirely after a tile's
+// last run start are skipped.
 // ---------------------------------------------------------------------------
+constexpr int kTilesPerItem = 4;
+
 template <int M>
 __global__ __launch_bounds__(kFwdThreads) void k_fwd_all(const uint32_t *__restrict__ tabs,
                                                          int32_t nblk,
@@ -156,31 +161,39 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_all(const uint32_t *__restr
     constexpr int CB = blocks_per_chunk<M>();
     __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
     if (sc->err) return;
-    const int32_t ic = blockIdx.x, jt = blockIdx.y;
+    const int32_t ic = blockIdx.y;
     const int32_t b0 = ic * CB;
     if (b0 >= nblk) return;
-    const int32_t tile0 = jt * kTileJ;
-    const int32_t tile_last = min(tile0 + kTileJ - 1, N - 1);
-    if (b0 * kBlk >= runstart[tile_last]) return;  // no candidate before any run start
+    const int32_t jt0 = (int32_t)blockIdx.x * kTilesPerItem;
+    const int32_t nJT = (N + kTileJ - 1) / kTileJ;
+    const int32_t jt1 = min(jt0 + kTilesPerItem, nJT);
+    // the chunk matters from the first tile whose last run start passes it
+    if (b0 * kBlk >= runstart[min(jt1 * kTileJ, N) - 1]) return;
     const int32_t nb = min(CB, nblk - b0);
     stage_tables<M>(lt, tabs, b0, nb);
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = (int)lane_id();
-    const int32_t jbase = tile0 + w * kWave * kTJ;
-    if (jbase >= N) return;
-    uint32_t kj[kTJ][M];
-    int32_t run[kTJ], cnt[kTJ];
-    load_points<M>(recs, runstart, N, jbase, lane, kj, run);
+    for (int32_t jt = jt0; jt < jt1; ++jt) {
+        const int32_t tile0 = jt * kTileJ;
+        const int32_t tile_last = min(tile0 + kTileJ - 1, N - 1);
+        if (b0 * kBlk >= runstart[tile_last]) continue;  // block-uniform
+        const int32_t jbase = tile0 + w * kWave * kTJ;
+        if (jbase >= N) continue;
+        uint32_t kj[kTJ][M];
+        int32_t run[kTJ], cnt[kTJ];
+        load_points<M>(recs, runstart, N, jbase, lane, kj, run);
 #pragma unroll
-    for (int t = 0; t < kTJ; ++t) cnt[t] = 0;
-    const int32_t run_lo = __builtin_amdgcn_readfirstlane(runstart[jbase]);
-    const int32_t run_hi = __builtin_amdgcn_readfirstlane(runstart[min(jbase + kWave * kTJ - 1, N - 1)]);
-    fwd_blocks<M>(lt, nb, run_lo, run_hi, kj, run, cnt);
+        for (int t = 0; t < kTJ; ++t) cnt[t] = 0;
+        const int32_t run_lo = __builtin_amdgcn_readfirstlane(runstart[jbase]);
+        const int32_t run_hi =
+            __builtin_amdgcn_readfirstlane(runstart[min(jbase + kWave * kTJ - 1, N - 1)]);
+        fwd_blocks<M>(lt, nb, run_lo, run_hi, kj, run, cnt);
 #pragma unroll
-    for (int t = 0; t < kTJ; ++t) {
-        const int32_t q = jbase + t * kWave + lane;
-        if (q < N && cnt[t]) atomicAdd(&dom_in[q], cnt[t]);
+        for (int t = 0; t < kTJ; ++t) {
+            const int32_t q = jbase + t * kWave + lane;
+            if (q < N && cnt[t]) atomicAdd(&dom_in[q], cnt[t]);
+        }
     }
 }
 
@@ -259,68 +272,75 @@ __global__ __launch_bounds__(kFwdThreads) void k_bwd_all(const uint32_t *__restr
                                                          const DevScalars *__restrict__ sc) {
     constexpr int TS = blk_stride(M);
     constexpr int CB = blocks_per_chunk<M>();
+    constexpr int MP = rec_stride(M);
     __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
     if (sc->err) return;
-    const int32_t jc = blockIdx.x, it = blockIdx.y;
+    const int32_t jc = blockIdx.y;
     const int32_t b0 = jc * CB;
     if (b0 >= nblk) return;
     const int32_t nb = min(CB, nblk - b0);
-    const int32_t tile0 = it * kTileJ;
+    const int32_t it0 = (int32_t)blockIdx.x * kTilesPerItem;
+    const int32_t nIT = (N + kTileJ - 1) / kTileJ;
+    const int32_t it1 = min(it0 + kTilesPerItem, nIT);
     const int32_t chunk_last = min((b0 + nb) * kBlk, N) - 1;
-    if (chunk_last < runend[tile0]) return;  // every member precedes every run end
+    if (chunk_last < runend[it0 * kTileJ]) return;  // every member precedes every run end
     stage_tables<M>(lt, tabs, b0, nb);
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = (int)lane_id();
-    const int32_t ibase = tile0 + w * kWave * kTJ;
-    if (ibase >= N) return;
-    constexpr int MP = rec_stride(M);
-    uint32_t ki[kTJ][M];
-    int32_t rend[kTJ], cnt[kTJ];
-#pragma unroll
-    for (int t = 0; t < kTJ; ++t) {
-        const int32_t q = ibase + t * kWave + lane;
-        cnt[t] = 0;
-        if (q < N) {
-#pragma unroll
-            for (int k = 0; k < M; ++k) ki[t][k] = recs[(size_t)q * MP + k];
-            rend[t] = runend[q];
-        } else {
-#pragma unroll
-            for (int k = 0; k < M; ++k) ki[t][k] = 0xffffffffu;
-            rend[t] = 0x7fffffff;  // dominates nothing
-        }
-    }
-    const int32_t rend_lo = __builtin_amdgcn_readfirstlane(runend[ibase]);
-    const int32_t rend_hi = __builtin_amdgcn_readfirstlane(runend[min(ibase + kWave * kTJ - 1, N - 1)]);
-    for (int32_t b = 0; b < nb; ++b) {
-        const uint32_t *T = lt + b * TS;
-        const int32_t bmin = (int32_t)T[0];
-        const int32_t bmax = (int32_t)T[1];
-        if (bmax < rend_lo) continue;  // the whole block precedes every run end
-        const uint64_t members = low_bits(T[2]);
-        const bool full = bmin >= rend_hi;
+    for (int32_t it = it0; it < it1; ++it) {
+        const int32_t tile0 = it * kTileJ;
+        if (chunk_last < runend[tile0]) break;  // later tiles end their runs later still
+        const int32_t ibase = tile0 + w * kWave * kTJ;
+        if (ibase >= N) break;
+        uint32_t ki[kTJ][M];
+        int32_t rend[kTJ], cnt[kTJ];
 #pragma unroll
         for (int t = 0; t < kTJ; ++t) {
-            uint64_t m = members;
-            if (!full) {
-                if (rend[t] > bmax) m = 0ull;
-                else if (rend[t] > bmin)
-                    m &= ~low_bits(count_pos_lt64(reinterpret_cast<const int32_t *>(T + blk_pos_off()),
-                                                  rend[t]));
-            }
+            const int32_t q = ibase + t * kWave + lane;
+            cnt[t] = 0;
+            if (q < N) {
 #pragma unroll
-            for (int k = 0; k < M; ++k) {
-                const uint32_t c = count_lt64(T + blk_key_off(k), ki[t][k]);
-                m &= ~reinterpret_cast<const uint64_t *>(T + blk_pm_off(M, k))[c];
+                for (int k = 0; k < M; ++k) ki[t][k] = recs[(size_t)q * MP + k];
+                rend[t] = runend[q];
+            } else {
+#pragma unroll
+                for (int k = 0; k < M; ++k) ki[t][k] = 0xffffffffu;
+                rend[t] = 0x7fffffff;  // dominates nothing
             }
-            cnt[t] += __popcll(m);
         }
-    }
+        const int32_t rend_lo = __builtin_amdgcn_readfirstlane(runend[ibase]);
+        const int32_t rend_hi =
+            __builtin_amdgcn_readfirstlane(runend[min(ibase + kWave * kTJ - 1, N - 1)]);
+        for (int32_t b = 0; b < nb; ++b) {
+            const uint32_t *T = lt + b * TS;
+            const int32_t bmin = (int32_t)T[0];
+            const int32_t bmax = (int32_t)T[1];
+            if (bmax < rend_lo) continue;  // the whole block precedes every run end
+            const uint64_t members = low_bits(T[2]);
+            const bool full = bmin >= rend_hi;
 #pragma unroll
-    for (int t = 0; t < kTJ; ++t) {
-        const int32_t q = ibase + t * kWave + lane;
-        if (q < N && cnt[t]) atomicAdd(&dom_out[q], cnt[t]);
+            for (int t = 0; t < kTJ; ++t) {
+                uint64_t m = members;
+                if (!full) {
+                    if (rend[t] > bmax) m = 0ull;
+                    else if (rend[t] > bmin)
+                        m &= ~low_bits(count_pos_lt64(reinterpret_cast<const int32_t *>(T + blk_pos_off()),
+                                                      rend[t]));
+                }
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    const uint32_t c = count_lt64(T + blk_key_off(k), ki[t][k]);
+                    m &= ~reinterpret_cast<const uint64_t *>(T + blk_pm_off(M, k))[c];
+                }
+                cnt[t] += __popcll(m);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kTJ; ++t) {
+            const int32_t q = ibase + t * kWave + lane;
+            if (q < N && cnt[t]) atomicAdd(&dom_out[q], cnt[t]);
+        }
     }
 }
 
@@ -336,10 +356,11 @@ static hipError_t launch_counts(const SortViews &v, hipStream_t s) {
                        (const int32_t *)nullptr, v.tabs_all, v.sc);
     const unsigned nIC = (unsigned)((nblk + CB - 1) / CB);
     const unsigned nJT = (unsigned)((N + kTileJ - 1) / kTileJ);
-    hipLaunchKernelGGL(k_fwd_all<M>, dim3(nIC, nJT), dim3(kFwdThreads), 0, s, v.tabs_all, nblk,
+    const unsigned nJG = (nJT + kTilesPerItem - 1) / kTilesPerItem;
+    hipLaunchKernelGGL(k_fwd_all<M>, dim3(nJG, nIC), dim3(kFwdThreads), 0, s, v.tabs_all, nblk,
                        v.recs, v.runstart, N, v.dom_in_s, v.sc);
     if (v.dom_out)
-        hipLaunchKernelGGL(k_bwd_all<M>, dim3(nIC, nJT), dim3(kFwdThreads), 0, s, v.tabs_all, nblk,
+        hipLaunchKernelGGL(k_bwd_all<M>, dim3(nJG, nIC), dim3(kFwdThreads), 0, s, v.tabs_all, nblk,
                            v.recs, v.runend, N, v.dom_out_s, v.sc);
     return hipGetLastError();
 }

@@ -37,10 +37,13 @@ enum EStage : int32_t {
     kSCmpC,       // selection flags: per-item counts
     kSCmpW,       // selection flags: ordered write
     kSSplit1,     // level split of a short list in one item (arg = level)
+    kSPeelTail,   // every remaining level in one item (arg = level already split)
     kSDone,
 };
 
 constexpr int kESplitOne = 4 * kESplit;  // lists up to this length split in one item
+constexpr int kETailDefault = 8192;      // default EInst::tail_max
+constexpr int kETailFrontDefault = 1024; // default EInst::tail_front
 
 // Per-instance scalars (in the instance's workspace).
 struct EScal {
@@ -126,6 +129,8 @@ struct EInst {
     int64_t K;
     int32_t N, M, H;
     int32_t pa_items;   // phase-A items a level aims for (chunk size adapts)
+    int32_t tail_max;   // remaining lists up to this length peel in one item (0: never) ...
+    int32_t tail_front; // ... when the current front has at most this many points
     ELayout L;          // elayout(N, M, H)
 };
 

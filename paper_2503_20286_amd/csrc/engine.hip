@@ -36,13 +36,22 @@ namespace {
 
 constexpr unsigned long long kIdleLimit = 400000000ull;  // wall-clock ticks (seconds at 100 MHz)
 
+// Uniform reads of data written inside the kernel.  A workgroup-scope atomic
+// load is a vector load that may hit the caches (which the claim's acquire
+// made current) but is never served by the scalar cache.
 template <typename T>
 __device__ __forceinline__ T ld(const T *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ double ldd(const double *p) {
     return __builtin_bit_cast(double, ld(reinterpret_cast<const uint64_t *>(p)));
+}
+
+// Reads of words other blocks update concurrently (progress words, counters).
+template <typename T>
+__device__ __forceinline__ T lda(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename T>
@@ -453,6 +462,96 @@ __device__ void item_split1(const EInst &I, int32_t k, int32_t n, uint32_t *smem
     }
 }
 
+// a2 tail: every remaining level of a short list in one item, with block
+// barriers only.  Starts after the split of level k (F_k and U_k in the
+// level-k lists); per level: F_k x U_k decrements (front chunks staged in
+// LDS; each remaining point belongs to one lane of a pass, so plain updates
+// suffice), then the split of level k + 1.  Writes the level sizes and the
+// number of fronts.
+template <int M>
+__device__ void item_peel_tail(const EInst &I, int32_t k, uint32_t *smem) {
+    const ELayout &L = I.L;
+    constexpr int MP = rec_stride(M);
+    constexpr int IC = 4096 / MP;  // front records per LDS chunk (16 KiB)
+    char *w = I.ws;
+    EScal *sc = at<EScal>(w, L.scal);
+    int32_t *fsize = at<int32_t>(w, L.fsize), *usize = at<int32_t>(w, L.usize);
+    int32_t *rank_s = at<int32_t>(w, L.rank_s);
+    uint32_t *lrec = smem;         // [IC * MP]
+    uint32_t *lds = smem + 4096;   // scan scratch
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = (int)lane_id();
+    int32_t nf = ld(&fsize[k]), nu = ld(&usize[k]);
+    for (;;) {
+        const bool odd = (k & 1) != 0;
+        const uint32_t *fk = at<uint32_t>(w, odd ? L.fk1 : L.fk0);
+        const uint32_t *uk = at<uint32_t>(w, odd ? L.uk1 : L.uk0);
+        const int32_t *urun = at<int32_t>(w, odd ? L.urun1 : L.urun0);
+        int32_t *ucnt = at<int32_t>(w, odd ? L.ucnt1 : L.ucnt0);
+        // each front chunk is staged once and swept over every remaining tile
+        // whose runs it can reach; the counts of a tile's points belong to one
+        // lane each, so the chunk's decrements are plain updates
+        for (int32_t f0 = 0; f0 < nf; f0 += IC) {
+            const int32_t f1 = min(f0 + IC, nf);
+            const int32_t fpos = (int32_t)ld(&fk[(size_t)f0 * MP + M]);
+            __syncthreads();  // the previous chunk is consumed
+            stage_recs<MP>(lrec, fk + (size_t)f0 * MP, f1 - f0);
+            __syncthreads();
+            for (int32_t j0 = 0; j0 < nu; j0 += kJT) {
+                const int32_t jbase = j0 + wv * kWave * kT;
+                if (jbase >= nu) break;
+                const int32_t run_hi = ld(&urun[min(jbase + kWave * kT - 1, nu - 1)]);
+                if (fpos >= run_hi) continue;  // the chunk starts after these runs
+                const int32_t run_lo = ld(&urun[jbase]);
+                uint32_t kj[kT][M];
+                int32_t run[kT], cin[kT];
+#pragma unroll
+                for (int t = 0; t < kT; ++t) {
+                    const int32_t q = jbase + t * kWave + lane;
+                    cin[t] = 0;
+                    if (q < nu) {
+#pragma unroll
+                        for (int kk = 0; kk < M; ++kk) kj[t][kk] = uk[(size_t)q * MP + kk];
+                        run[t] = urun[q];
+                    } else {
+#pragma unroll
+                        for (int kk = 0; kk < M; ++kk) kj[t][kk] = 0u;
+                        run[t] = 0;
+                    }
+                }
+                tile_rows_bounded<M>(lrec, f1 - f0, run_lo, run_hi, kj, run, cin);
+#pragma unroll
+                for (int t = 0; t < kT; ++t) {
+                    const int32_t q = jbase + t * kWave + lane;
+                    if (q < nu && cin[t]) ucnt[q] -= cin[t];
+                }
+            }
+        }
+        __syncthreads();
+        const LevelLists s = level_lists(w, L, k + 1);
+        uint32_t of = 0, ou = 0;
+        for (int32_t e0 = 0; e0 < nu; e0 += kESplit) {
+            uint32_t a, b;
+            split_chunk<M>(s, k + 1, e0, min(e0 + kESplit, nu), of, ou, rank_s, lds, &a, &b);
+            of += a;
+            ou += b;
+        }
+        ++k;
+        if (threadIdx.x == 0) {
+            fsize[k] = (int32_t)of;
+            usize[k] = (int32_t)ou;
+        }
+        nf = (int32_t)of;
+        nu = (int32_t)ou;
+        if (nu == 0 || nf == 0) break;  // nf == 0 with nu > 0 cannot happen; flagged below
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sc->num_fronts = k + 1;
+        if (nu != 0) atomicOr(&sc->err, (uint32_t)kErrInternal);
+    }
+}
+
 // a2: F_k x U_k decrements for one (front chunk, remaining tile) item.
 template <int M>
 __device__ void item_phase_a(const EInst &I, int32_t k, int32_t IC, int32_t nJT,
@@ -773,6 +872,7 @@ __device__ void run_item(const EInst &I, int32_t stage, int32_t arg, int32_t n,
         case kSSplitC: item_splitc(I, arg, n, t, smem); break;
         case kSSplitW: item_splitw<M>(I, arg, n, t, smem); break;
         case kSSplit1: item_split1<M>(I, arg, n, smem); break;
+        case kSPeelTail: item_peel_tail<M>(I, arg, smem); break;
         case kSPhaseA: item_phase_a<M>(I, arg, p0, p1, t, smem); break;
         case kSOrig: item_orig(I, t); break;
         case kSExt: item_ext<M>(I, t, smem); break;
@@ -997,6 +1097,9 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, int32_t stop_stag
         } else if (U == 0) {
             stage = kSOrig;
             items = cdiv(N, kEChunk);
+        } else if (U <= I.tail_max && F <= I.tail_front) {
+            stage = kSPeelTail;
+            items = 1;
         } else {
             const int32_t nJT = (int32_t)cdiv(U, kJT);
             int32_t IC = 4096 / MP;
@@ -1058,6 +1161,29 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, int32_t stop_stag
             case kSPhaseA:
                 begin_level(arg + 1, n);
                 break;
+            case kSPeelTail: {
+                // a3 for the levels the tail peeled (level arg was counted already)
+                if (threadIdx.x == 0) {
+                    const int32_t nfr = ld(&sc->num_fronts);
+                    const int32_t *fsz = at<int32_t>(w, L.fsize);
+                    int64_t cum = ld(&sc->n_before);
+                    for (int32_t lv = arg + 1; lv < nfr && ld(&sc->last_front) < 0; ++lv) {
+                        const int32_t F = ld(&fsz[lv]);
+                        if (cum + (int64_t)F >= I.K) {
+                            sc->last_front = lv;
+                            sc->last_front_size = F;
+                            sc->R = I.K - cum;
+                        } else {
+                            cum += F;
+                        }
+                    }
+                    sc->n_before = cum;
+                }
+                __syncthreads();
+                stage = kSOrig;
+                items = cdiv(N, kEChunk);
+                break;
+            }
             case kSOrig:
                 stage = kSExt; items = cdiv(N, kEChunk);
                 break;
@@ -1136,7 +1262,7 @@ __global__ __launch_bounds__(kEThreads) void k_engine(const EInst *__restrict__ 
             // the instance this block worked on last comes first: its next
             // items are usually ready
             if (lane == 0) {
-                const uint64_t wd = ld(&st[b0 + cursor].word);
+                const uint64_t wd = lda(&st[b0 + cursor].word);
                 if ((uint32_t)(wd >> 32) < (uint32_t)wd) {
                     const uint64_t old = __hip_atomic_fetch_add(&st[b0 + cursor].word, 1ull << 32,
                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1159,7 +1285,7 @@ __global__ __launch_bounds__(kEThreads) void k_engine(const EInst *__restrict__ 
                     if (off < nb) {
                         int32_t q = start + off;
                         q -= q >= nb ? nb : 0;
-                        const uint64_t wd = ld(&st[b0 + q].word);
+                        const uint64_t wd = lda(&st[b0 + q].word);
                         ok = (uint32_t)(wd >> 32) < (uint32_t)wd;
                     }
                     m[r] = ballot(ok);
@@ -1202,7 +1328,7 @@ __global__ __launch_bounds__(kEThreads) void k_engine(const EInst *__restrict__ 
         if (b < 0) {
             if (threadIdx.x == 0) {
                 uint32_t stop = 0;
-                if (ld(&g->finished) >= (uint32_t)nb || ld(&g->err) != 0) {
+                if (lda(&g->finished) >= (uint32_t)nb || lda(&g->err) != 0) {
                     stop = 1;
                 } else {
                     const long long now = wall_clock64();

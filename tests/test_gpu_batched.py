@@ -161,6 +161,27 @@ def test_engine_bad_instance_is_isolated():
     plan.close()
 
 
+def test_autotuned_plan_matches_single_calls():
+    """Autotuning picks work-item shapes by timing; results must not change."""
+    import torch
+    import paper_2503_20286_amd as nsga3
+    ws = workloads.make_batch(18, n_lo=100, n_hi=12000, base_seed=8200)
+    probs = _dev(ws)
+    ctx = nsga3.Context(0, autotune=True)
+    plan = nsga3.Plan(probs, ctx=ctx)
+    for rep in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        _check_against_single(plan, probs, ("autotuned", rep))
+    plan2 = nsga3.Plan(probs, ctx=ctx)  # tuned shapes come from the context's cache
+    plan2.launch()
+    torch.cuda.synchronize()
+    _check_against_single(plan2, probs, "cached")
+    plan.close()
+    plan2.close()
+    ctx.close()
+
+
 def test_plan_rejects_bad_descriptor():
     import torch
     import paper_2503_20286_amd as nsga3
