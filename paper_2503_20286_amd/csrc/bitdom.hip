@@ -69,9 +69,13 @@ __global__ __launch_bounds__(64) void k_build_blocks(const uint32_t *__restrict_
             const uint64_t t = __shfl_up(bit, o, 64);
             if (l >= o) bit |= t;
         }
-        uint64_t *pm = reinterpret_cast<uint64_t *>(T + blk_pm_off(M, k));
-        pm[l + 1] = bit;
-        if (l == 0) pm[0] = 0ull;
+        uint32_t *pm = T + blk_pm_off(M, k);
+        pm[l + 1] = (uint32_t)bit;
+        pm[65 + l + 1] = (uint32_t)(bit >> 32);
+        if (l == 0) {
+            pm[0] = 0u;
+            pm[65] = 0u;
+        }
         __syncthreads();
     }
 }
@@ -100,6 +104,17 @@ __device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32
         const int32_t bmax = (int32_t)T[1];
         if (bmin >= run_hi) break;  // later blocks start later still
         const bool full = bmax < run_lo;
+        // the kTJ x M key searches in lockstep
+        const uint32_t *S[kTJ * M];
+        uint32_t x[kTJ * M], c[kTJ * M];
+#pragma unroll
+        for (int t = 0; t < kTJ; ++t)
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                S[t * M + k] = T + blk_key_off(k);
+                x[t * M + k] = kj[t][k];
+            }
+        count_many64<kTJ * M, true>(S, x, c);
 #pragma unroll
         for (int t = 0; t < kTJ; ++t) {
             uint64_t m = ~0ull;
@@ -110,10 +125,7 @@ __device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32
                                                 run[t]));
             }
 #pragma unroll
-            for (int k = 0; k < M; ++k) {
-                const uint32_t c = count_le64(T + blk_key_off(k), kj[t][k]);
-                m &= reinterpret_cast<const uint64_t *>(T + blk_pm_off(M, k))[c];
-            }
+            for (int k = 0; k < M; ++k) m &= prefix_mask(T + blk_pm_off(M, k), c[t * M + k]);
             cnt[t] += __popcll(m);
         }
     }
@@ -142,13 +154,15 @@ __device__ __forceinline__ void load_points(const uint32_t *__restrict__ jrec,
 }
 
 // ---------------------------------------------------------------------------
-// In-degrees over all points.  Grid: x = group of kTilesPerItem point tiles,
-// y = block chunk, so that neighbouring work-groups share the chunk staged in
-// LDS (read from L2 once per XCD instead of once per tile); each work-group
-// reuses its chunk for kTilesPerItem tiles.  Chunks entirely after a tile's
-// last run start are skipped.
+// In-degrees over all points.  A work-group owns kTilesPerItem point tiles
+// (their keys stay in registers) and sweeps kChunksPerItem consecutive block
+// chunks, staging each in LDS once; its counts go out with one atomic per
+// point.  Grid: x = tile group, y = chunk group, so neighbouring work-groups
+// share their chunks in L2.  Chunks entirely after a tile's last run start
+// are skipped.
 // ---------------------------------------------------------------------------
 constexpr int kTilesPerItem = 4;
+constexpr int kChunksPerItem = 2;
 
 template <int M>
 __global__ __launch_bounds__(kFwdThreads) void k_fwd_all(const uint32_t *__restrict__ tabs,
@@ -159,40 +173,50 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_all(const uint32_t *__restr
                                                          const DevScalars *__restrict__ sc) {
     constexpr int TS = blk_stride(M);
     constexpr int CB = blocks_per_chunk<M>();
+    constexpr int T = kTilesPerItem;
     __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
     if (sc->err) return;
-    const int32_t ic = blockIdx.y;
-    const int32_t b0 = ic * CB;
-    if (b0 >= nblk) return;
-    const int32_t jt0 = (int32_t)blockIdx.x * kTilesPerItem;
     const int32_t nJT = (N + kTileJ - 1) / kTileJ;
-    const int32_t jt1 = min(jt0 + kTilesPerItem, nJT);
-    // the chunk matters from the first tile whose last run start passes it
-    if (b0 * kBlk >= runstart[min(jt1 * kTileJ, N) - 1]) return;
-    const int32_t nb = min(CB, nblk - b0);
-    stage_tables<M>(lt, tabs, b0, nb);
-    __syncthreads();
+    const int32_t nIC = (nblk + CB - 1) / CB;
+    const int32_t jt0 = (int32_t)blockIdx.x * T;
+    const int32_t c0 = (int32_t)blockIdx.y * kChunksPerItem;
+    const int32_t c1 = min(c0 + kChunksPerItem, nIC);
+    if (c0 >= nIC) return;
+    const int32_t last_run = runstart[min((jt0 + T) * kTileJ, N) - 1];
+    if (c0 * CB * kBlk >= last_run) return;  // every chunk starts after every run
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = (int)lane_id();
-    for (int32_t jt = jt0; jt < jt1; ++jt) {
-        const int32_t tile0 = jt * kTileJ;
-        const int32_t tile_last = min(tile0 + kTileJ - 1, N - 1);
-        if (b0 * kBlk >= runstart[tile_last]) continue;  // block-uniform
-        const int32_t jbase = tile0 + w * kWave * kTJ;
-        if (jbase >= N) continue;
-        uint32_t kj[kTJ][M];
-        int32_t run[kTJ], cnt[kTJ];
-        load_points<M>(recs, runstart, N, jbase, lane, kj, run);
+    uint32_t kj[T][kTJ][M];
+    int32_t run[T][kTJ], cnt[T][kTJ], run_lo[T], run_hi[T];
 #pragma unroll
-        for (int t = 0; t < kTJ; ++t) cnt[t] = 0;
-        const int32_t run_lo = __builtin_amdgcn_readfirstlane(runstart[jbase]);
-        const int32_t run_hi =
-            __builtin_amdgcn_readfirstlane(runstart[min(jbase + kWave * kTJ - 1, N - 1)]);
-        fwd_blocks<M>(lt, nb, run_lo, run_hi, kj, run, cnt);
+    for (int t = 0; t < T; ++t) {
+        const int32_t jbase = (jt0 + t) * kTileJ + w * kWave * kTJ;
+        load_points<M>(recs, runstart, N, jbase, lane, kj[t], run[t]);
 #pragma unroll
-        for (int t = 0; t < kTJ; ++t) {
-            const int32_t q = jbase + t * kWave + lane;
-            if (q < N && cnt[t]) atomicAdd(&dom_in[q], cnt[t]);
+        for (int u = 0; u < kTJ; ++u) cnt[t][u] = 0;
+        const int32_t jb = min(jbase, N - 1);
+        run_lo[t] = __builtin_amdgcn_readfirstlane(runstart[jb]);
+        run_hi[t] = jbase < N ? __builtin_amdgcn_readfirstlane(
+                                    runstart[min(jbase + kWave * kTJ - 1, N - 1)])
+                              : 0;  // no points: no chunk reaches them
+    }
+    for (int32_t c = c0; c < c1; ++c) {
+        const int32_t b0 = c * CB;
+        if (b0 * kBlk >= last_run) break;  // later chunks start later still
+        const int32_t nb = min(CB, nblk - b0);
+        __syncthreads();  // the previous chunk is consumed
+        stage_tables<M>(lt, tabs, b0, nb);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+            if (b0 * kBlk < run_hi[t]) fwd_blocks<M>(lt, nb, run_lo[t], run_hi[t], kj[t], run[t], cnt[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+        for (int u = 0; u < kTJ; ++u) {
+            const int32_t q = (jt0 + t) * kTileJ + w * kWave * kTJ + u * kWave + lane;
+            if (q < N && cnt[t][u]) atomicAdd(&dom_in[q], cnt[t][u]);
         }
     }
 }
@@ -263,6 +287,48 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
 // members j count when every key of j is >= i's and j lies in a later run
 // (position >= runend(i)).
 // ---------------------------------------------------------------------------
+// Backward probe of the staged blocks for one group of kTJ earlier points per
+// lane: members j with every key >= i's and a position >= runend(i).
+template <int M>
+__device__ __forceinline__ void bwd_blocks(const uint32_t *lt, int32_t nb, int32_t rend_lo,
+                                           int32_t rend_hi, const uint32_t (&ki)[kTJ][M],
+                                           const int32_t (&rend)[kTJ], int32_t (&cnt)[kTJ]) {
+    constexpr int TS = blk_stride(M);
+    for (int32_t b = 0; b < nb; ++b) {
+        const uint32_t *T = lt + b * TS;
+        const int32_t bmin = (int32_t)T[0];
+        const int32_t bmax = (int32_t)T[1];
+        if (bmax < rend_lo) continue;  // the whole block precedes every run end
+        const uint64_t members = low_bits(T[2]);
+        const bool full = bmin >= rend_hi;
+        const uint32_t *S[kTJ * M];
+        uint32_t x[kTJ * M], c[kTJ * M];
+#pragma unroll
+        for (int t = 0; t < kTJ; ++t)
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                S[t * M + k] = T + blk_key_off(k);
+                x[t * M + k] = ki[t][k];
+            }
+        count_many64<kTJ * M, false>(S, x, c);
+#pragma unroll
+        for (int t = 0; t < kTJ; ++t) {
+            uint64_t m = members;
+            if (!full) {
+                if (rend[t] > bmax) m = 0ull;
+                else if (rend[t] > bmin)
+                    m &= ~low_bits(count_pos_lt64(reinterpret_cast<const int32_t *>(T + blk_pos_off()),
+                                                  rend[t]));
+            }
+#pragma unroll
+            for (int k = 0; k < M; ++k) m &= ~prefix_mask(T + blk_pm_off(M, k), c[t * M + k]);
+            cnt[t] += __popcll(m);
+        }
+    }
+}
+
+// Out-degrees over all points: each lane an earlier point i, later blocks;
+// same work-group shape as the in-degree kernel.
 template <int M>
 __global__ __launch_bounds__(kFwdThreads) void k_bwd_all(const uint32_t *__restrict__ tabs,
                                                          int32_t nblk,
@@ -273,73 +339,63 @@ __global__ __launch_bounds__(kFwdThreads) void k_bwd_all(const uint32_t *__restr
     constexpr int TS = blk_stride(M);
     constexpr int CB = blocks_per_chunk<M>();
     constexpr int MP = rec_stride(M);
+    constexpr int T = kTilesPerItem;
     __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
     if (sc->err) return;
-    const int32_t jc = blockIdx.y;
-    const int32_t b0 = jc * CB;
-    if (b0 >= nblk) return;
-    const int32_t nb = min(CB, nblk - b0);
-    const int32_t it0 = (int32_t)blockIdx.x * kTilesPerItem;
-    const int32_t nIT = (N + kTileJ - 1) / kTileJ;
-    const int32_t it1 = min(it0 + kTilesPerItem, nIT);
-    const int32_t chunk_last = min((b0 + nb) * kBlk, N) - 1;
-    if (chunk_last < runend[it0 * kTileJ]) return;  // every member precedes every run end
-    stage_tables<M>(lt, tabs, b0, nb);
-    __syncthreads();
+    const int32_t nIC = (nblk + CB - 1) / CB;
+    const int32_t it0 = (int32_t)blockIdx.x * T;
+    const int32_t c0 = (int32_t)blockIdx.y * kChunksPerItem;
+    const int32_t c1 = min(c0 + kChunksPerItem, nIC);
+    if (c0 >= nIC || it0 * kTileJ >= N) return;
+    const int32_t first_end = runend[it0 * kTileJ];  // smallest run end of the group
+    if (min(c1 * CB * kBlk, N) - 1 < first_end) return;  // every member precedes every run end
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = (int)lane_id();
-    for (int32_t it = it0; it < it1; ++it) {
-        const int32_t tile0 = it * kTileJ;
-        if (chunk_last < runend[tile0]) break;  // later tiles end their runs later still
-        const int32_t ibase = tile0 + w * kWave * kTJ;
-        if (ibase >= N) break;
-        uint32_t ki[kTJ][M];
-        int32_t rend[kTJ], cnt[kTJ];
+    uint32_t ki[T][kTJ][M];
+    int32_t rend[T][kTJ], cnt[T][kTJ], rend_lo[T], rend_hi[T];
 #pragma unroll
-        for (int t = 0; t < kTJ; ++t) {
-            const int32_t q = ibase + t * kWave + lane;
-            cnt[t] = 0;
+    for (int t = 0; t < T; ++t) {
+        const int32_t ibase = (it0 + t) * kTileJ + w * kWave * kTJ;
+#pragma unroll
+        for (int u = 0; u < kTJ; ++u) {
+            const int32_t q = ibase + u * kWave + lane;
+            cnt[t][u] = 0;
             if (q < N) {
 #pragma unroll
-                for (int k = 0; k < M; ++k) ki[t][k] = recs[(size_t)q * MP + k];
-                rend[t] = runend[q];
+                for (int k = 0; k < M; ++k) ki[t][u][k] = recs[(size_t)q * MP + k];
+                rend[t][u] = runend[q];
             } else {
 #pragma unroll
-                for (int k = 0; k < M; ++k) ki[t][k] = 0xffffffffu;
-                rend[t] = 0x7fffffff;  // dominates nothing
+                for (int k = 0; k < M; ++k) ki[t][u][k] = 0xffffffffu;
+                rend[t][u] = 0x7fffffff;  // dominates nothing
             }
         }
-        const int32_t rend_lo = __builtin_amdgcn_readfirstlane(runend[ibase]);
-        const int32_t rend_hi =
-            __builtin_amdgcn_readfirstlane(runend[min(ibase + kWave * kTJ - 1, N - 1)]);
-        for (int32_t b = 0; b < nb; ++b) {
-            const uint32_t *T = lt + b * TS;
-            const int32_t bmin = (int32_t)T[0];
-            const int32_t bmax = (int32_t)T[1];
-            if (bmax < rend_lo) continue;  // the whole block precedes every run end
-            const uint64_t members = low_bits(T[2]);
-            const bool full = bmin >= rend_hi;
-#pragma unroll
-            for (int t = 0; t < kTJ; ++t) {
-                uint64_t m = members;
-                if (!full) {
-                    if (rend[t] > bmax) m = 0ull;
-                    else if (rend[t] > bmin)
-                        m &= ~low_bits(count_pos_lt64(reinterpret_cast<const int32_t *>(T + blk_pos_off()),
-                                                      rend[t]));
-                }
-#pragma unroll
-                for (int k = 0; k < M; ++k) {
-                    const uint32_t c = count_lt64(T + blk_key_off(k), ki[t][k]);
-                    m &= ~reinterpret_cast<const uint64_t *>(T + blk_pm_off(M, k))[c];
-                }
-                cnt[t] += __popcll(m);
-            }
+        if (ibase < N) {
+            rend_lo[t] = __builtin_amdgcn_readfirstlane(runend[ibase]);
+            rend_hi[t] = __builtin_amdgcn_readfirstlane(runend[min(ibase + kWave * kTJ - 1, N - 1)]);
+        } else {
+            rend_lo[t] = 0x7fffffff;  // no points: every block precedes
+            rend_hi[t] = 0x7fffffff;
         }
+    }
+    for (int32_t c = c0; c < c1; ++c) {
+        const int32_t b0 = c * CB;
+        const int32_t nb = min(CB, nblk - b0);
+        const int32_t chunk_last = min((b0 + nb) * kBlk, N) - 1;
+        if (chunk_last < first_end) continue;  // precedes every run end of the group
+        __syncthreads();  // the previous chunk is consumed
+        stage_tables<M>(lt, tabs, b0, nb);
+        __syncthreads();
 #pragma unroll
-        for (int t = 0; t < kTJ; ++t) {
-            const int32_t q = ibase + t * kWave + lane;
-            if (q < N && cnt[t]) atomicAdd(&dom_out[q], cnt[t]);
+        for (int t = 0; t < T; ++t)
+            if (chunk_last >= rend_lo[t]) bwd_blocks<M>(lt, nb, rend_lo[t], rend_hi[t], ki[t], rend[t], cnt[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+        for (int u = 0; u < kTJ; ++u) {
+            const int32_t q = (it0 + t) * kTileJ + w * kWave * kTJ + u * kWave + lane;
+            if (q < N && cnt[t][u]) atomicAdd(&dom_out[q], cnt[t][u]);
         }
     }
 }
@@ -357,10 +413,11 @@ static hipError_t launch_counts(const SortViews &v, hipStream_t s) {
     const unsigned nIC = (unsigned)((nblk + CB - 1) / CB);
     const unsigned nJT = (unsigned)((N + kTileJ - 1) / kTileJ);
     const unsigned nJG = (nJT + kTilesPerItem - 1) / kTilesPerItem;
-    hipLaunchKernelGGL(k_fwd_all<M>, dim3(nJG, nIC), dim3(kFwdThreads), 0, s, v.tabs_all, nblk,
+    const unsigned nCG = (nIC + kChunksPerItem - 1) / kChunksPerItem;
+    hipLaunchKernelGGL(k_fwd_all<M>, dim3(nJG, nCG), dim3(kFwdThreads), 0, s, v.tabs_all, nblk,
                        v.recs, v.runstart, N, v.dom_in_s, v.sc);
     if (v.dom_out)
-        hipLaunchKernelGGL(k_bwd_all<M>, dim3(nJG, nIC), dim3(kFwdThreads), 0, s, v.tabs_all, nblk,
+        hipLaunchKernelGGL(k_bwd_all<M>, dim3(nJG, nCG), dim3(kFwdThreads), 0, s, v.tabs_all, nblk,
                            v.recs, v.runend, N, v.dom_out_s, v.sc);
     return hipGetLastError();
 }
