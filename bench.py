@@ -8,12 +8,15 @@ directions (p=6), K=100,000; sphere shell f = r*u, r = 1 + Exp(rate 4), 20% of
 points with r = 1), inputs resident in device memory.
 
 Prints one JSON line (rank 0, N=1).  The roofline object covers the dominant
-kernel (pairwise dominance counting): algorithmic compares M*N*(N-1)/2 per
-launch divided by the kernel's average duration from HIP events recorded on
-the library's stream, against the vector-ALU compare peak
-256 CUs x 64 lanes x 2.4 GHz.  The CPU baseline is the float64 oracle on a
-bounded sample of the same recipe, scaled to N=200,000 by the O(N^2) cost of
-its dominance stages.
+phase (the dominance counts: block-table build, in-degree and out-degree
+kernels): algorithmic work M*N*(N-1)/2 pair-objective compares per launch
+(every unordered pair decided once) divided by the phase's duration from HIP
+events the library records on its stream, against the vector-ALU compare
+peak 256 CUs x 64 lanes x 2.4 GHz; traffic is the phase's HBM bytes from
+FETCH_SIZE / WRITE_SIZE counters (profiles/dominance_count_large_traffic.json).
+The "batched" object times 512 selections of mixed N and M in one graph
+launch.  The CPU baseline is the float64 oracle on a bounded sample of the
+same recipe, scaled to N=200,000 by the O(N^2) cost of its dominance stages.
 """
 from __future__ import annotations
 
@@ -351,13 +354,16 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_domcount (pairwise dominance counts)",
+            "kernel": "dominance counts (k_build_blocks + k_fwd_all + k_bwd_all, block bitsets)",
             "achieved": achieved,
             "peak": peak,
             "unit": "Tcmp/s",
             "frac": achieved / peak,
             "traffic": traffic,
-            "work_per_launch": f"{cmp_per_launch:.4e} compares (M*N*(N-1)/2)",
+            "work_per_launch": f"{cmp_per_launch:.4e} pair-objective compares (M*N*(N-1)/2: every "
+                               "unordered pair decided once)",
+            "frac_counts_and_peeling": cmp_per_launch / ((phases["dominance_count"] + phases["peel"])
+                                                          / 1e3) / PEAK_CMP_PER_S,
         },
         "phases_ms": phases,
         "fronts": {"num_fronts": info.num_fronts, "last_front": info.last_front,
