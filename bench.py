@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large", choices=["large", "many", "ties", "small"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-n", type=int, default=60000)
+    ap.add_argument("--cpu-sample-n", type=int, default=140000)
     ap.add_argument("--check", action="store_true", help="verify one timed result (sampled)")
     ap.add_argument("--assoc", default="fp32", choices=["fp32", "bf16"],
                     help="association screening precision (re-scoring is float64 in both)")

@@ -195,8 +195,8 @@ nsga3_status nsga3_tuned_shapes(const nsga3_ctx *ctx, int32_t *out, int32_t cap,
  *   8 outputs in original order, 9 extreme points, 10 association,
  *   11 bucket scatter, 12 niche picks, 13 compaction counts, 14 compaction
  *   writes, 15 short-list split in one item, 16 remaining levels in one item,
- *   17 done. */
-#define NSGA3_PLAN_STAGES 18
+ *   17 two-objective ranks in one ordered pass, 18 done. */
+#define NSGA3_PLAN_STAGES 19
 
 /* Diagnostics of a plan created while profiling was enabled: per stage, the
  * block-milliseconds spent inside its work items and its epilogues, and the

@@ -16,7 +16,11 @@ constexpr int kERsTile = 2048;     // keys per radix-sort item
 constexpr int kESplit = 2048;      // list entries per split item
 constexpr int kECmp = 2048;        // flags per compaction item
 constexpr int kESmem = 12288;      // LDS dwords per worker block
-constexpr int kERadixPasses = 5;   // key sums need at most 36 bits for M <= 16
+// Presort key: the exact key sum (at most 36 bits for M <= 16, five 8-bit
+// passes); for M = 2 the lexicographic pair (key_1, key_2) (eight passes),
+// which is also a linear extension of dominance and lets the fronts be found
+// in one ordered pass (kSRank2).
+__host__ __device__ constexpr int radix_passes(int M) { return M == 2 ? 8 : 5; }
 
 __host__ __device__ constexpr int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -38,6 +42,7 @@ enum EStage : int32_t {
     kSCmpW,       // selection flags: ordered write
     kSSplit1,     // level split of a short list in one item (arg = level)
     kSPeelTail,   // every remaining level in one item (arg = level already split)
+    kSRank2,      // M = 2: every rank in one ordered pass (one item)
     kSDone,
 };
 
@@ -53,6 +58,7 @@ struct EScal {
     int64_t n_before, R;
     int32_t near_ties, level_V, ref_thr;
     uint32_t n_selected;
+    int32_t rank2_overflow;  // the ordered pass found more fronts than it can hold
     double z[16], a[16];
 };
 

@@ -120,6 +120,11 @@ __device__ void item_prep(const EInst &I, int32_t t, uint32_t *smem) {
                 s += key;
                 lmin[k] = key < lmin[k] ? key : lmin[k];
             }
+            if (M == 2) {  // lexicographic pair (see radix_passes)
+                const uint32_t k0 = order_key(I.objs[(int64_t)p * M]);
+                const uint32_t k1 = order_key(I.objs[(int64_t)p * M + 1]);
+                s = ((uint64_t)k0 << 32) | (uint64_t)k1;
+            }
             skey[p] = s;
             sval[p] = (uint32_t)p;
             din[p] = 0;
@@ -229,8 +234,9 @@ __device__ void item_recs(const EInst &I, int32_t t) {
     constexpr int MP = rec_stride(M);
     char *w = I.ws;
     const int32_t N = I.N;
-    const uint64_t *skey = at<uint64_t>(w, L.skey1);
-    const uint32_t *sval = at<uint32_t>(w, L.sval1);
+    const bool odd = (radix_passes(M) & 1) != 0;  // where the last pass wrote
+    const uint64_t *skey = at<uint64_t>(w, odd ? L.skey1 : L.skey0);
+    const uint32_t *sval = at<uint32_t>(w, odd ? L.sval1 : L.sval0);
     uint32_t *recs = at<uint32_t>(w, L.recs);
     int32_t *runstart = at<int32_t>(w, L.runstart);
     for (int q = 0; q < kEChunk / kEThreads; ++q) {
@@ -552,6 +558,83 @@ __device__ void item_peel_tail(const EInst &I, int32_t k, uint32_t *smem) {
     }
 }
 
+// a2 for two objectives: the points are in lexicographic (key_1, key_2)
+// order, so every earlier point has key_1 <= the current one and a front
+// dominates the current point p iff its smallest key_2 so far is <= p's
+// (equality means an identical point, which is always p's predecessor, and
+// identical points share a rank).  The smallest key_2 per front, T2, never
+// decreases with the front index, so p's rank is the number of fronts with
+// T2 <= key_2(p), found by a two-level lane-parallel count, and p lowers T2
+// of its front.  One wave, one ordered pass; ranks equal the peeling levels.
+template <int M>
+__device__ void item_rank2(const EInst &I, uint32_t *smem) {
+    if constexpr (M != 2) return;  // only two-objective instances take this stage
+    const ELayout &L = I.L;
+    char *w = I.ws;
+    EScal *sc = at<EScal>(w, L.scal);
+    const int32_t N = I.N;
+    const uint32_t *recs = at<uint32_t>(w, L.recs);  // [key_1, key_2, position, 0]
+    int32_t *rank_s = at<int32_t>(w, L.rank_s);
+    constexpr int CAP = kESmem / 2;
+    uint32_t *T2 = smem;         // [CAP]
+    uint32_t *cnt = smem + CAP;  // [CAP] front sizes
+    if (threadIdx.x >= kWave) return;
+    const int lane = (int)lane_id();
+    int32_t nf = 0;
+    bool overflow = false;
+    uint32_t pa = 0, pb = 0;
+    int32_t prank = -1;
+    for (int32_t base = 0; base < N && !overflow; base += kWave) {
+        const int32_t p = base + lane;
+        uint32_t a = 0, b = 0;
+        if (p < N) {
+            a = recs[(size_t)p * 4];
+            b = recs[(size_t)p * 4 + 1];
+        }
+        const int32_t n_here = min(kWave, N - base);
+        int32_t myrank = 0;
+        for (int32_t t = 0; t < n_here; ++t) {
+            const uint32_t ka = __shfl(a, t, 64), kb = __shfl(b, t, 64);
+            int32_t r;
+            if (prank >= 0 && ka == pa && kb == pb) {
+                r = prank;
+            } else if (nf <= kWave) {
+                const bool dom = lane < nf && T2[lane] <= kb;
+                r = (int32_t)__popcll(ballot(dom));
+            } else {
+                const int32_t s = (nf + kWave - 1) / kWave;  // sample stride
+                const int32_t q = lane * s;
+                const int32_t c1 = (int32_t)__popcll(ballot(q < nf && T2[q] <= kb));
+                const int32_t lo = c1 == 0 ? 0 : (c1 - 1) * s + 1;
+                const int32_t hi = c1 == 0 ? 0 : min(c1 * s, nf);
+                const int32_t q2 = lo + lane;
+                r = lo + (int32_t)__popcll(ballot(q2 < hi && T2[q2] <= kb));
+            }
+            if (r == nf) {
+                if (nf == CAP) { overflow = true; break; }
+                if (lane == 0) cnt[nf] = 0;
+                ++nf;
+            }
+            if (lane == 0) {
+                T2[r] = kb;
+                cnt[r] += 1;
+            }
+            if (lane == t) myrank = r;
+            pa = ka;
+            pb = kb;
+            prank = r;
+        }
+        if (!overflow && p < N) rank_s[p] = myrank;
+    }
+    int32_t *fsize = at<int32_t>(w, L.fsize);
+    if (!overflow)
+        for (int32_t r = lane; r < nf; r += kWave) fsize[r] = (int32_t)cnt[r];
+    if (lane == 0) {
+        sc->rank2_overflow = overflow ? 1 : 0;
+        sc->num_fronts = overflow ? 0 : nf;
+    }
+}
+
 // a2: F_k x U_k decrements for one (front chunk, remaining tile) item.
 template <int M>
 __device__ void item_phase_a(const EInst &I, int32_t k, int32_t IC, int32_t nJT,
@@ -608,7 +691,7 @@ __device__ void item_phase_a(const EInst &I, int32_t k, int32_t IC, int32_t nJT,
 __device__ void item_orig(const EInst &I, int32_t t) {
     const ELayout &L = I.L;
     char *w = I.ws;
-    const uint32_t *sval = at<uint32_t>(w, L.sval1);
+    const uint32_t *sval = at<uint32_t>(w, (radix_passes(I.M) & 1) ? L.sval1 : L.sval0);
     const int32_t *rank_s = at<int32_t>(w, L.rank_s);
     const int32_t *din = at<int32_t>(w, L.din), *dout = at<int32_t>(w, L.dout);
     int32_t *rank = I.rank ? I.rank : at<int32_t>(w, L.rank);
@@ -873,6 +956,7 @@ __device__ void run_item(const EInst &I, int32_t stage, int32_t arg, int32_t n,
         case kSSplitW: item_splitw<M>(I, arg, n, t, smem); break;
         case kSSplit1: item_split1<M>(I, arg, n, smem); break;
         case kSPeelTail: item_peel_tail<M>(I, arg, smem); break;
+        case kSRank2: item_rank2<M>(I, smem); break;
         case kSPhaseA: item_phase_a<M>(I, arg, p0, p1, t, smem); break;
         case kSOrig: item_orig(I, t); break;
         case kSExt: item_ext<M>(I, t, smem); break;
@@ -1124,7 +1208,7 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, int32_t stop_stag
                 stage = kSScat; items = cdiv(N, kERsTile);
                 break;
             case kSScat:
-                if (arg + 1 < kERadixPasses) { stage = kSHist; ++arg; items = cdiv(N, kERsTile); }
+                if (arg + 1 < radix_passes(M)) { stage = kSHist; ++arg; items = cdiv(N, kERsTile); }
                 else { stage = kSRecs; items = cdiv(N, kEChunk); }
                 break;
             case kSRecs: {
@@ -1161,6 +1245,13 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, int32_t stop_stag
             case kSPhaseA:
                 begin_level(arg + 1, n);
                 break;
+            case kSRank2:
+                if (ld(&sc->rank2_overflow)) {  // too many fronts for the ordered pass
+                    begin_level(0, N);
+                    break;
+                }
+                arg = -1;  // every level is still to be counted
+                // fall through: a3 over the fronts the pass found
             case kSPeelTail: {
                 // a3 for the levels the tail peeled (level arg was counted already)
                 if (threadIdx.x == 0) {
@@ -1409,6 +1500,7 @@ __global__ void k_engine_init(const EInst *__restrict__ inst, EState *st, EGloba
     sc->level_V = 0;
     sc->ref_thr = 0;
     sc->n_selected = 0;
+    sc->rank2_overflow = 0;
     EState &S = st[b];
     S.stage = kSPrep;
     S.arg = 0;
@@ -1448,11 +1540,15 @@ __global__ void k_engine_resume(const EInst *__restrict__ inst, EState *st, int3
     }
     sc->n_before = 0;
     sc->last_front = -1;
+    sc->rank2_overflow = 0;
     S.arg = 0;
     S.n = I.N;
     S.p0 = S.p1 = 0;
     S.done = 0;
-    if (I.N <= kESplitOne) {
+    if (I.M == 2) {
+        S.stage = kSRank2;
+        S.word = 1ull;
+    } else if (I.N <= kESplitOne) {
         S.stage = kSSplit1;
         S.word = 1ull;
     } else {
