@@ -24,6 +24,9 @@ struct nsga3_plan {
     nsga3::EState *d_state = nullptr;
     nsga3::EGlobal *d_glob = nullptr;    // two per objective count (before / after the counts)
     int2 *d_map = nullptr;               // (instance, item) of every dominance-count block
+    int2 *d_bmap = nullptr;              // (instance, block) of every block-table build
+    int2 *d_cmap = nullptr;              // (instance, work-group) of the bitset count kernels
+    bool bitdom = true;                  // block-bitset counts (else pairwise items)
     nsga3::EStats *d_stats = nullptr;    // engine diagnostics (plans created while profiling)
     int clock_khz = 0;
     std::vector<void *> ws;
@@ -524,6 +527,8 @@ static void plan_free(nsga3_plan *pl) {
     if (pl->d_state) (void)hipFree(pl->d_state);
     if (pl->d_glob) (void)hipFree(pl->d_glob);
     if (pl->d_map) (void)hipFree(pl->d_map);
+    if (pl->d_bmap) (void)hipFree(pl->d_bmap);
+    if (pl->d_cmap) (void)hipFree(pl->d_cmap);
     if (pl->d_stats) (void)hipFree(pl->d_stats);
     delete pl;
 }
@@ -545,9 +550,15 @@ static nsga3_status tune_group(nsga3_ctx *ctx, const std::vector<nsga3::EInst> &
                                hipStream_t s, EngineShape *best) {
     using namespace nsga3;
     const int32_t nb = (int32_t)group.size();
-    std::vector<int2> map;
-    for (int32_t q = 0; q < nb; ++q)
-        for (int64_t t = 0; t < engine_dom_items(group[q].N); ++t) map.push_back(make_int2(q, (int)t));
+    std::vector<int2> map, cmap;  // block-table builds, count work-groups
+    for (int32_t q = 0; q < nb; ++q) {
+        int64_t nbld = 0, ncnt = 0;
+        engine_bitdom_items(group[q].N, group[q].M, &nbld, &ncnt);
+        for (int64_t t = 0; t < nbld; ++t) map.push_back(make_int2(q, (int)t));
+        for (int64_t t = 0; t < ncnt; ++t) cmap.push_back(make_int2(q, (int)t));
+    }
+    const size_t nmap = map.size();
+    map.insert(map.end(), cmap.begin(), cmap.end());
     EInst *d_inst = nullptr;
     EState *d_state = nullptr;
     EGlobal *d_glob = nullptr;
@@ -584,7 +595,9 @@ static nsga3_status tune_group(nsga3_ctx *ctx, const std::vector<nsga3::EInst> &
             hipError_t e = hipEventRecord(e0, s);
             if (e == hipSuccess) e = engine_init(d_inst, d_state, d_glob, nb, 2, s);
             if (e == hipSuccess) e = engine_launch(M, d_inst, d_state, 0, nb, d_glob, nullptr, kSDom, grid, s);
-            if (e == hipSuccess) e = engine_dom_launch(M, d_inst, d_state, d_map, (int64_t)map.size(), s);
+            if (e == hipSuccess)
+                e = engine_bitdom_launch(M, d_inst, d_state, d_map, (int64_t)nmap, d_map + nmap,
+                                         (int64_t)cmap.size(), s);
             if (e == hipSuccess) e = engine_resume(d_inst, d_state, 0, nb, d_glob + 1, s);
             if (e == hipSuccess) e = engine_launch(M, d_inst, d_state, 0, nb, d_glob + 1, nullptr, kSDone, grid, s);
             if (e == hipSuccess) e = hipEventRecord(e1, s);
@@ -685,6 +698,22 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
         }
     }
     map_off[nclass] = (int64_t)map.size();
+    // block-bitset form: table builds and count work-groups per class
+    std::vector<int2> bmap, cmap;
+    std::vector<int64_t> boff(nclass + 1, 0), coff(nclass + 1, 0);
+    for (int c = 0; c < nclass; ++c) {
+        boff[c] = (int64_t)bmap.size();
+        coff[c] = (int64_t)cmap.size();
+        for (int32_t q = cls[c].first; q < cls[c].first + cls[c].second; ++q) {
+            int64_t nbld = 0, ncnt = 0;
+            engine_bitdom_items(inst[q].N, inst[q].M, &nbld, &ncnt);
+            for (int64_t t = 0; t < nbld; ++t) bmap.push_back(make_int2(q, (int)t));
+            for (int64_t t = 0; t < ncnt; ++t) cmap.push_back(make_int2(q, (int)t));
+        }
+    }
+    boff[nclass] = (int64_t)bmap.size();
+    coff[nclass] = (int64_t)cmap.size();
+    pl->bitdom = !(getenv("NSGA3_PAIRWISE") && atoi(getenv("NSGA3_PAIRWISE")) != 0);
     if (hipMalloc((void **)&pl->d_glob, sizeof(EGlobal) * (size_t)(2 * nclass)) != hipSuccess ||
         hipMalloc((void **)&pl->d_map, sizeof(int2) * (map.size() ? map.size() : 1)) != hipSuccess) {
         (void)hipGetLastError();
@@ -692,6 +721,16 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
     }
     if (!map.empty() &&
         hipMemcpy(pl->d_map, map.data(), sizeof(int2) * map.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return NSGA3_E_HIP;
+    if (hipMalloc((void **)&pl->d_bmap, sizeof(int2) * (bmap.size() ? bmap.size() : 1)) != hipSuccess ||
+        hipMalloc((void **)&pl->d_cmap, sizeof(int2) * (cmap.size() ? cmap.size() : 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return NSGA3_E_NOMEM;
+    }
+    if ((!bmap.empty() && hipMemcpy(pl->d_bmap, bmap.data(), sizeof(int2) * bmap.size(),
+                                    hipMemcpyHostToDevice) != hipSuccess) ||
+        (!cmap.empty() && hipMemcpy(pl->d_cmap, cmap.data(), sizeof(int2) * cmap.size(),
+                                    hipMemcpyHostToDevice) != hipSuccess))
         return NSGA3_E_HIP;
     if (ctx->opt.autotune) {
         // shapes per (M, N range): tune the groups the context has not seen
@@ -773,9 +812,16 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
     }
     // phase 2: the dominance counts of every instance, with no engine running
     // (the engines' cache invalidations would keep these launches' data cold)
-    for (int c = 0; c < nclass && e == hipSuccess; ++c)
-        e = engine_dom_launch(inst[cls[c].first].M, pl->d_inst, pl->d_state, pl->d_map + map_off[c],
-                              map_off[c + 1] - map_off[c], pl->cap);
+    for (int c = 0; c < nclass && e == hipSuccess; ++c) {
+        const int M = inst[cls[c].first].M;
+        if (pl->bitdom)
+            e = engine_bitdom_launch(M, pl->d_inst, pl->d_state, pl->d_bmap + boff[c],
+                                     boff[c + 1] - boff[c], pl->d_cmap + coff[c],
+                                     coff[c + 1] - coff[c], pl->cap);
+        else
+            e = engine_dom_launch(M, pl->d_inst, pl->d_state, pl->d_map + map_off[c],
+                                  map_off[c + 1] - map_off[c], pl->cap);
+    }
     if (e == hipSuccess) e = hipEventRecord(ev[2 * nclass + 1], pl->cap);
     // phase 3 (branch per class): peeling, normalisation, association, niching, output
     for (int c = 0; c < nclass && e == hipSuccess; ++c) {

@@ -9,6 +9,7 @@
 // i lies before the run of points sharing j's key sum (identical rows and
 // equal-sum points never dominate each other).
 #include "bitdom.h"
+#include "engine.h"
 #include "kernels.h"
 #include "prims.h"
 
@@ -28,17 +29,10 @@ __host__ __device__ constexpr int blocks_per_chunk() {
 // Tables: one wave per block of 64 consecutive list entries.
 // ---------------------------------------------------------------------------
 template <int M>
-__global__ __launch_bounds__(64) void k_build_blocks(const uint32_t *__restrict__ rec,
-                                                     int32_t n_static,
-                                                     const int32_t *__restrict__ n_dev,
-                                                     uint32_t *__restrict__ tabs,
-                                                     const DevScalars *__restrict__ sc) {
+__device__ __forceinline__ void build_block(const uint32_t *__restrict__ rec, int32_t n,
+                                            uint32_t *__restrict__ tabs, int32_t b, int32_t *inv) {
     constexpr int MP = rec_stride(M);
     constexpr int TS = blk_stride(M);
-    __shared__ int32_t inv[kBlk];
-    if (sc->err) return;
-    const int32_t n = n_static >= 0 ? n_static : *n_dev;
-    const int32_t b = blockIdx.x;
     if ((int64_t)b * kBlk >= n) return;
     const int l = threadIdx.x;
     const int32_t e = b * kBlk + l;
@@ -78,6 +72,18 @@ __global__ __launch_bounds__(64) void k_build_blocks(const uint32_t *__restrict_
         }
         __syncthreads();
     }
+}
+
+template <int M>
+__global__ __launch_bounds__(64) void k_build_blocks(const uint32_t *__restrict__ rec,
+                                                     int32_t n_static,
+                                                     const int32_t *__restrict__ n_dev,
+                                                     uint32_t *__restrict__ tabs,
+                                                     const DevScalars *__restrict__ sc) {
+    __shared__ int32_t inv[kBlk];
+    if (sc->err) return;
+    const int32_t n = n_static >= 0 ? n_static : *n_dev;
+    build_block<M>(rec, n, tabs, (int32_t)blockIdx.x, inv);
 }
 
 // Stage `nb` consecutive tables into LDS.
@@ -165,21 +171,16 @@ constexpr int kTilesPerItem = 4;
 constexpr int kChunksPerItem = 2;
 
 template <int M>
-__global__ __launch_bounds__(kFwdThreads) void k_fwd_all(const uint32_t *__restrict__ tabs,
-                                                         int32_t nblk,
-                                                         const uint32_t *__restrict__ recs,
-                                                         const int32_t *__restrict__ runstart,
-                                                         int32_t N, int32_t *__restrict__ dom_in,
-                                                         const DevScalars *__restrict__ sc) {
-    constexpr int TS = blk_stride(M);
+__device__ __forceinline__ void fwd_all_item(const uint32_t *__restrict__ tabs, int32_t nblk,
+                                             const uint32_t *__restrict__ recs,
+                                             const int32_t *__restrict__ runstart, int32_t N,
+                                             int32_t *__restrict__ dom_in, int32_t jg, int32_t cg,
+                                             uint32_t *lt) {
     constexpr int CB = blocks_per_chunk<M>();
     constexpr int T = kTilesPerItem;
-    __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
-    if (sc->err) return;
-    const int32_t nJT = (N + kTileJ - 1) / kTileJ;
     const int32_t nIC = (nblk + CB - 1) / CB;
-    const int32_t jt0 = (int32_t)blockIdx.x * T;
-    const int32_t c0 = (int32_t)blockIdx.y * kChunksPerItem;
+    const int32_t jt0 = jg * T;
+    const int32_t c0 = cg * kChunksPerItem;
     const int32_t c1 = min(c0 + kChunksPerItem, nIC);
     if (c0 >= nIC) return;
     const int32_t last_run = runstart[min((jt0 + T) * kTileJ, N) - 1];
@@ -219,6 +220,18 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_all(const uint32_t *__restr
             if (q < N && cnt[t][u]) atomicAdd(&dom_in[q], cnt[t][u]);
         }
     }
+}
+
+template <int M>
+__global__ __launch_bounds__(kFwdThreads) void k_fwd_all(const uint32_t *__restrict__ tabs,
+                                                         int32_t nblk,
+                                                         const uint32_t *__restrict__ recs,
+                                                         const int32_t *__restrict__ runstart,
+                                                         int32_t N, int32_t *__restrict__ dom_in,
+                                                         const DevScalars *__restrict__ sc) {
+    __shared__ __attribute__((aligned(16))) uint32_t lt[blocks_per_chunk<M>() * blk_stride(M)];
+    if (sc->err) return;
+    fwd_all_item<M>(tabs, nblk, recs, runstart, N, dom_in, (int32_t)blockIdx.x, (int32_t)blockIdx.y, lt);
 }
 
 // ---------------------------------------------------------------------------
@@ -330,21 +343,17 @@ __device__ __forceinline__ void bwd_blocks(const uint32_t *lt, int32_t nb, int32
 // Out-degrees over all points: each lane an earlier point i, later blocks;
 // same work-group shape as the in-degree kernel.
 template <int M>
-__global__ __launch_bounds__(kFwdThreads) void k_bwd_all(const uint32_t *__restrict__ tabs,
-                                                         int32_t nblk,
-                                                         const uint32_t *__restrict__ recs,
-                                                         const int32_t *__restrict__ runend,
-                                                         int32_t N, int32_t *__restrict__ dom_out,
-                                                         const DevScalars *__restrict__ sc) {
-    constexpr int TS = blk_stride(M);
+__device__ __forceinline__ void bwd_all_item(const uint32_t *__restrict__ tabs, int32_t nblk,
+                                             const uint32_t *__restrict__ recs,
+                                             const int32_t *__restrict__ runend, int32_t N,
+                                             int32_t *__restrict__ dom_out, int32_t jg, int32_t cg,
+                                             uint32_t *lt) {
     constexpr int CB = blocks_per_chunk<M>();
     constexpr int MP = rec_stride(M);
     constexpr int T = kTilesPerItem;
-    __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
-    if (sc->err) return;
     const int32_t nIC = (nblk + CB - 1) / CB;
-    const int32_t it0 = (int32_t)blockIdx.x * T;
-    const int32_t c0 = (int32_t)blockIdx.y * kChunksPerItem;
+    const int32_t it0 = jg * T;
+    const int32_t c0 = cg * kChunksPerItem;
     const int32_t c1 = min(c0 + kChunksPerItem, nIC);
     if (c0 >= nIC || it0 * kTileJ >= N) return;
     const int32_t first_end = runend[it0 * kTileJ];  // smallest run end of the group
@@ -398,6 +407,106 @@ __global__ __launch_bounds__(kFwdThreads) void k_bwd_all(const uint32_t *__restr
             if (q < N && cnt[t][u]) atomicAdd(&dom_out[q], cnt[t][u]);
         }
     }
+}
+
+template <int M>
+__global__ __launch_bounds__(kFwdThreads) void k_bwd_all(const uint32_t *__restrict__ tabs,
+                                                         int32_t nblk,
+                                                         const uint32_t *__restrict__ recs,
+                                                         const int32_t *__restrict__ runend,
+                                                         int32_t N, int32_t *__restrict__ dom_out,
+                                                         const DevScalars *__restrict__ sc) {
+    __shared__ __attribute__((aligned(16))) uint32_t lt[blocks_per_chunk<M>() * blk_stride(M)];
+    if (sc->err) return;
+    bwd_all_item<M>(tabs, nblk, recs, runend, N, dom_out, (int32_t)blockIdx.x, (int32_t)blockIdx.y, lt);
+}
+
+// ---------------------------------------------------------------------------
+// Batched form for the engine's parked instances (one map entry per
+// work-group; instances that finished early are skipped).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T *inst_at(const EInst &I, size_t off) {
+    return reinterpret_cast<T *>(I.ws + off);
+}
+
+template <int M>
+__global__ __launch_bounds__(64) void k_eng_build(const EInst *__restrict__ inst,
+                                                  const EState *__restrict__ st,
+                                                  const int2 *__restrict__ map) {
+    __shared__ int32_t inv[kBlk];
+    const int2 e = map[blockIdx.x];
+    if (st[e.x].stage != kSDom) return;
+    const EInst &I = inst[e.x];
+    build_block<M>(inst_at<const uint32_t>(I, I.L.recs), I.N, inst_at<uint32_t>(I, I.L.tabs), e.y, inv);
+}
+
+template <int M, bool kOut>
+__global__ __launch_bounds__(kFwdThreads) void k_eng_count(const EInst *__restrict__ inst,
+                                                           const EState *__restrict__ st,
+                                                           const int2 *__restrict__ map) {
+    constexpr int CB = blocks_per_chunk<M>();
+    __shared__ __attribute__((aligned(16))) uint32_t lt[CB * blk_stride(M)];
+    const int2 e = map[blockIdx.x];
+    if (st[e.x].stage != kSDom) return;
+    const EInst &I = inst[e.x];
+    const int32_t N = I.N;
+    const int32_t nblk = (N + kBlk - 1) / kBlk;
+    const int32_t nCG = ((nblk + CB - 1) / CB + kChunksPerItem - 1) / kChunksPerItem;
+    const int32_t jg = e.y / nCG, cg = e.y % nCG;
+    const uint32_t *tabs = inst_at<const uint32_t>(I, I.L.tabs);
+    const uint32_t *recs = inst_at<const uint32_t>(I, I.L.recs);
+    if (kOut)
+        bwd_all_item<M>(tabs, nblk, recs, inst_at<const int32_t>(I, I.L.runend), N,
+                        inst_at<int32_t>(I, I.L.dout), jg, cg, lt);
+    else
+        fwd_all_item<M>(tabs, nblk, recs, inst_at<const int32_t>(I, I.L.runstart), N,
+                        inst_at<int32_t>(I, I.L.din), jg, cg, lt);
+}
+
+template <int M>
+static hipError_t launch_eng_bitdom(const EInst *inst, const EState *st, const int2 *bmap,
+                                    int64_t nb_build, const int2 *cmap, int64_t nb_count,
+                                    hipStream_t s) {
+    if (nb_build > 0)
+        hipLaunchKernelGGL(k_eng_build<M>, dim3((unsigned)nb_build), dim3(64), 0, s, inst, st, bmap);
+    if (nb_count > 0) {
+        hipLaunchKernelGGL((k_eng_count<M, false>), dim3((unsigned)nb_count), dim3(kFwdThreads), 0, s,
+                           inst, st, cmap);
+        hipLaunchKernelGGL((k_eng_count<M, true>), dim3((unsigned)nb_count), dim3(kFwdThreads), 0, s,
+                           inst, st, cmap);
+    }
+    return hipGetLastError();
+}
+
+hipError_t engine_bitdom_launch(int M, const EInst *inst, const EState *st, const int2 *bmap,
+                                int64_t nb_build, const int2 *cmap, int64_t nb_count,
+                                hipStream_t s) {
+    switch (M) {
+#define NSGA3_CASE(m) case m: return launch_eng_bitdom<m>(inst, st, bmap, nb_build, cmap, nb_count, s);
+        NSGA3_CASE(2) NSGA3_CASE(3) NSGA3_CASE(4) NSGA3_CASE(5) NSGA3_CASE(6) NSGA3_CASE(7)
+        NSGA3_CASE(8) NSGA3_CASE(9) NSGA3_CASE(10) NSGA3_CASE(11) NSGA3_CASE(12) NSGA3_CASE(13)
+        NSGA3_CASE(14) NSGA3_CASE(15) NSGA3_CASE(16)
+#undef NSGA3_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+void engine_bitdom_items(int64_t N, int M, int64_t *n_build, int64_t *n_count) {
+    int cb = 1;
+    switch (M) {
+#define NSGA3_CB(m) case m: cb = blocks_per_chunk<m>(); break;
+        NSGA3_CB(2) NSGA3_CB(3) NSGA3_CB(4) NSGA3_CB(5) NSGA3_CB(6) NSGA3_CB(7) NSGA3_CB(8)
+        NSGA3_CB(9) NSGA3_CB(10) NSGA3_CB(11) NSGA3_CB(12) NSGA3_CB(13) NSGA3_CB(14) NSGA3_CB(15)
+        NSGA3_CB(16)
+#undef NSGA3_CB
+        default: break;
+    }
+    const int64_t nblk = (N + kBlk - 1) / kBlk;
+    const int64_t nJG = ((N + kTileJ - 1) / kTileJ + kTilesPerItem - 1) / kTilesPerItem;
+    const int64_t nCG = ((nblk + cb - 1) / cb + kChunksPerItem - 1) / kChunksPerItem;
+    *n_build = nblk;
+    *n_count = nJG * nCG;
 }
 
 // ---------------------------------------------------------------------------

@@ -64,7 +64,7 @@ struct EScal {
 
 // Byte offsets of one instance's arrays inside its workspace.
 struct ELayout {
-    size_t skey0, skey1, sval0, sval1, hist, recs, runstart, din, dout, rank_s;
+    size_t skey0, skey1, sval0, sval1, hist, recs, runstart, runend, tabs, din, dout, rank_s;
     size_t fk0, fk1, uk0, uk1, urun0, urun1, ucnt0, ucnt1, spc, fsize, usize;
     size_t rank, niche, dist64, p_asf, p_idx, p_nad, rhat64, rhat32;
     size_t rho, bcount, bstart, bcursor, bd, bi, selflag, cmpc, scal, total;
@@ -89,6 +89,8 @@ __host__ __device__ inline ELayout elayout(int64_t N, int M, int H) {
     L.hist = bump(4 * 256 * nrs);
     L.recs = bump(4 * n * MP);
     L.runstart = bump(4 * n);
+    L.runend = bump(4 * n);
+    L.tabs = bump(4 * (size_t)cdiv(N, 64) * (size_t)(((68 + 194 * M) + 3) / 4 * 4));
     L.din = bump(4 * n);
     L.dout = bump(4 * n);
     L.rank_s = bump(4 * n);
@@ -177,6 +179,15 @@ hipError_t engine_dom_launch(int M, const EInst *inst, const EState *st, const i
 // already done count as finished in g.
 hipError_t engine_resume(const EInst *inst, EState *st, int32_t b0, int32_t nb, EGlobal *g,
                          hipStream_t s);
+// Block-bitset dominance counts of every parked instance (bitdom.hip): block
+// tables (bmap[q] = (instance, block), nb_build entries), then in-degrees and
+// out-degrees (cmap[q] = (instance, work-group), nb_count entries).
+hipError_t engine_bitdom_launch(int M, const EInst *inst, const EState *st, const int2 *bmap,
+                                int64_t nb_build, const int2 *cmap, int64_t nb_count,
+                                hipStream_t s);
+// Block tables and count work-groups of one instance for the launch above.
+void engine_bitdom_items(int64_t N, int M, int64_t *n_build, int64_t *n_count);
+
 // Number of dominance items of an instance of N points.
 inline int64_t engine_dom_items(int64_t N) {
     const int64_t T = cdiv(N, 1024);

@@ -239,6 +239,7 @@ __device__ void item_recs(const EInst &I, int32_t t) {
     const uint32_t *sval = at<uint32_t>(w, odd ? L.sval1 : L.sval0);
     uint32_t *recs = at<uint32_t>(w, L.recs);
     int32_t *runstart = at<int32_t>(w, L.runstart);
+    int32_t *runend = at<int32_t>(w, L.runend);
     for (int q = 0; q < kEChunk / kEThreads; ++q) {
         const int32_t p = t * kEChunk + q * kEThreads + (int32_t)threadIdx.x;
         if (p >= N) break;
@@ -257,6 +258,13 @@ __device__ void item_recs(const EInst &I, int32_t t) {
             if (skey[mid] < me) lo = mid + 1; else hi = mid;
         }
         runstart[p] = lo;
+        lo = p + 1;  // first position with a larger key
+        hi = N;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (skey[mid] <= me) lo = mid + 1; else hi = mid;
+        }
+        runend[p] = lo;
     }
 }
 
