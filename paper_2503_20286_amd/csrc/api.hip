@@ -75,7 +75,7 @@ struct Layout {
     size_t runend, tabs_all, tabs_lvl;
     size_t lb_stride;
     size_t rank, niche, dist64, rhat64, rhat32, rhat16, p_asf, p_idx, p_nad;
-    size_t rho, bcount, bstart, bcursor, bd, bi, selflag, sc, bar;
+    size_t rho, bcount, bstart, bcursor, gstart, bd, bi, selflag, sc, bar;
     size_t total;
 };
 
@@ -134,6 +134,7 @@ Layout layout_for(int64_t N, int M, int H, int max_grid) {
     L.bcount = bump(c, 4 * (size_t)H);
     L.bstart = bump(c, 4 * ((size_t)H + 1));
     L.bcursor = bump(c, 4 * (size_t)H);
+    L.gstart = bump(c, 4 * ((size_t)H + 1));
     L.bd = bump(c, 8 * n);
     L.bi = bump(c, 4 * n);
     L.selflag = bump(c, n);
@@ -327,6 +328,7 @@ hipError_t enqueue_select(const EnqArgs &a, const nsga3_problem &p, hipStream_t 
     xv.bcount = WS(int32_t, bcount);
     xv.bstart = WS(int32_t, bstart);
     xv.bcursor = WS(int32_t, bcursor);
+    xv.gstart = WS(int32_t, gstart);
     xv.bd = WS(double, bd);
     xv.bi = WS(int32_t, bi);
     xv.selflag = WS(uint8_t, selflag);

@@ -777,6 +777,8 @@ __device__ void item_ext(const EInst &I, int32_t t, uint32_t *smem) {
 
 // a6/a7: association of one point per thread; the float32 unit references
 // pass through LDS in chunks, twice (maximum, then candidates).
+static_assert(8192 + 2 * kLdsNicheRefs <= kESmem, "association LDS: reference chunk + tallies");
+
 template <int M>
 __device__ void item_assoc(const EInst &I, int32_t t, uint32_t *smem) {
     const ELayout &L = I.L;
@@ -842,32 +844,30 @@ __device__ void item_assoc(const EInst &I, int32_t t, uint32_t *smem) {
             }
         }
     }
-    if (!inr) return;
     int32_t *niche = I.niche ? I.niche : at<int32_t>(w, L.niche);
     double *dist64 = at<double>(w, L.dist64);
     uint8_t *selflag = at<uint8_t>(w, L.selflag);
-    if (!active) {
+    int cls = -1;
+    if (active) {
+        niche[i] = best;
+        if (I.dist) I.dist[i] = (float)d1;
+        dist64[i] = d1;
+        if (near_tie(d1, d2)) atomicAdd(&sc->near_ties, 1);
+        cls = r < l ? 0 : 1;
+        selflag[i] = r < l ? 1 : 0;
+    } else if (inr) {
         niche[i] = -1;
         if (I.dist) I.dist[i] = -1.0f;
         dist64[i] = -1.0;
         selflag[i] = 0;
-        return;
     }
-    niche[i] = best;
-    if (I.dist) I.dist[i] = (float)d1;
-    dist64[i] = d1;
-    if (near_tie(d1, d2)) atomicAdd(&sc->near_ties, 1);
-    if (r < l) {
-        atomicAdd(&at<int32_t>(w, L.rho)[best], 1);
-        selflag[i] = 1;
-    } else {
-        atomicAdd(&at<int32_t>(w, L.bcount)[best], 1);
-        selflag[i] = 0;
-    }
+    // the tallies sit past the reference chunk, which other waves may still read
+    niche_count_block(H, cls, best, at<int32_t>(w, L.rho), at<int32_t>(w, L.bcount),
+                      reinterpret_cast<int32_t *>(smem) + 8192);
 }
 
 // Last-front members into their reference buckets.
-__device__ void item_bscat(const EInst &I, int32_t t) {
+__device__ void item_bscat(const EInst &I, int32_t t, uint32_t *smem) {
     const ELayout &L = I.L;
     char *w = I.ws;
     EScal *sc = at<EScal>(w, L.scal);
@@ -880,11 +880,14 @@ __device__ void item_bscat(const EInst &I, int32_t t) {
     int32_t *bi = at<int32_t>(w, L.bi);
     for (int q = 0; q < kEChunk / kEThreads; ++q) {
         const int32_t i = t * kEChunk + q * kEThreads + (int32_t)threadIdx.x;
-        if (i >= I.N) break;
-        if (rank[i] != l) continue;
-        const int32_t slot = atomicAdd(&bcursor[niche[i]], 1);
-        bd[slot] = dist64[i];
-        bi[slot] = i;
+        const bool member = i < I.N && rank[i] == l;
+        const int32_t b = member ? niche[i] : 0;
+        const int32_t slot =
+            bucket_slot_block(I.H, member, b, bcursor, reinterpret_cast<int32_t *>(smem));
+        if (member) {
+            bd[slot] = dist64[i];
+            bi[slot] = i;
+        }
     }
 }
 
@@ -969,7 +972,7 @@ __device__ void run_item(const EInst &I, int32_t stage, int32_t arg, int32_t n,
         case kSOrig: item_orig(I, t); break;
         case kSExt: item_ext<M>(I, t, smem); break;
         case kSAssoc: item_assoc<M>(I, t, smem); break;
-        case kSBScat: item_bscat(I, t); break;
+        case kSBScat: item_bscat(I, t, smem); break;
         case kSBRank: item_brank(I, t); break;
         case kSCmpC: item_cmpc(I, t, smem); break;
         case kSCmpW: item_cmpw(I, t, smem); break;
@@ -1030,15 +1033,18 @@ __device__ void epi_solve(const EInst &I, EScal *sc, uint32_t *smem) {
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double z[16], a[16];
-        for (int k = 0; k < M; ++k) {
-            z[k] = (double)key_to_float(ld(&sc->min_key[k]));
-            sc->z[k] = z[k];
+    if (threadIdx.x < kWave) {
+        double z[M], a[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) z[k] = (double)key_to_float(ld(&sc->min_key[k]));
+        const int fb = solve_intercepts_wave<M>(I.objs, s_e, s_nad, z, a);
+        if (threadIdx.x == 0) {
+            for (int k = 0; k < M; ++k) {
+                sc->z[k] = z[k];
+                sc->a[k] = a[k];
+            }
+            sc->fallback = fb;
         }
-        const int fb = solve_intercepts(I.objs, M, s_e, s_nad, z, a);
-        for (int k = 0; k < M; ++k) sc->a[k] = a[k];
-        sc->fallback = fb;
     }
     __syncthreads();
 }

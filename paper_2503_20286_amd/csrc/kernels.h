@@ -97,6 +97,7 @@ struct SelectViews {
     int32_t *p_idx;              // [nb * M]
     double *p_nad;               // [nb * M]
     int32_t *rho, *bcount, *bstart, *bcursor;  // [H], [H], [H+1], [H]
+    int32_t *gstart;             // [H+1] first rank work-group of each bucket
     double *bd;                  // [N] bucketed distances
     int32_t *bi;                 // [N] bucketed indices
     uint8_t *selflag;            // [N]

@@ -29,6 +29,7 @@
 namespace nsga3 {
 
 constexpr int kNormThreads = 256;
+constexpr int kRankGroup = 256;  // bucket members ranked per work-group
 constexpr int kNormBlocksMax = 256;
 
 // ---------------------------------------------------------------------------
@@ -169,21 +170,29 @@ __global__ __launch_bounds__(kNormThreads) void k_extreme_partial(
 
 // ---------------------------------------------------------------------------
 // a5: reduce the partials, build E, solve E b = 1, intercepts / fallback.
-// One wave.
+// One block of kSolveThreads: every thread folds its share of the partials
+// for all axes, the waves fold across lanes, wave 0 across waves.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_solve(const float *__restrict__ objs, int M, int nparts,
-                                              const double *__restrict__ p_asf,
-                                              const int32_t *__restrict__ p_idx,
-                                              const double *__restrict__ p_nad,
-                                              DevScalars *__restrict__ sc) {
+constexpr int kSolveThreads = 1024;
+
+template <int M>
+__global__ __launch_bounds__(kSolveThreads) void k_solve(const float *__restrict__ objs, int nparts,
+                                                         const double *__restrict__ p_asf,
+                                                         const int32_t *__restrict__ p_idx,
+                                                         const double *__restrict__ p_nad,
+                                                         DevScalars *__restrict__ sc) {
+    constexpr int kW = kSolveThreads / kWave;
+    __shared__ double w_asf[kW][16], w_nad[kW][16];
+    __shared__ int32_t w_idx[kW][16];
     __shared__ int32_t s_e[16];
     __shared__ double s_nadir[16];
     if (sc->err) return;
+    const int lane = (int)lane_id(), wid = (int)threadIdx.x / kWave;
     for (int j = 0; j < M; ++j) {
         double b = DBL_MAX;
         int32_t bi = 0x7fffffff;
         double nd = 0.0;
-        for (int q = threadIdx.x; q < nparts; q += 64) {
+        for (int q = threadIdx.x; q < nparts; q += kSolveThreads) {
             const double a = p_asf[q * M + j];
             const int32_t ai = p_idx[q * M + j];
             if (a < b || (a == b && ai < bi)) { b = a; bi = ai; }
@@ -197,24 +206,40 @@ __global__ __launch_bounds__(64) void k_solve(const float *__restrict__ objs, in
             const double on = __shfl_xor(nd, o, 64);
             nd = on > nd ? on : nd;
         }
-        if (threadIdx.x == 0) { s_e[j] = bi; s_nadir[j] = nd; }
+        if (lane == 0) { w_asf[wid][j] = b; w_idx[wid][j] = bi; w_nad[wid][j] = nd; }
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    double z[16], a[16];
-    for (int k = 0; k < M; ++k) { z[k] = ideal(sc, k); sc->z[k] = z[k]; }
-    const int fb = solve_intercepts(objs, M, s_e, s_nadir, z, a);
-    for (int k = 0; k < M; ++k) sc->a[k] = a[k];
+    if (wid != 0) return;
+    for (int j = 0; j < M; ++j) {
+        double b = lane < kW ? w_asf[lane][j] : DBL_MAX;
+        int32_t bi = lane < kW ? w_idx[lane][j] : 0x7fffffff;
+        double nd = lane < kW ? w_nad[lane][j] : 0.0;
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(b, o, 64);
+            const int32_t oi = __shfl_xor(bi, o, 64);
+            if (ob < b || (ob == b && oi < bi)) { b = ob; bi = oi; }
+            const double on = __shfl_xor(nd, o, 64);
+            nd = on > nd ? on : nd;
+        }
+        if (lane == 0) { s_e[j] = bi; s_nadir[j] = nd; }
+    }
+    double z[M], a[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) z[k] = ideal(sc, k);
+    const int fb = solve_intercepts_wave<M>(objs, s_e, s_nadir, z, a);
+    if (lane != 0) return;
+    for (int k = 0; k < M; ++k) {
+        sc->z[k] = z[k];
+        sc->a[k] = a[k];
+    }
     sc->fallback = fb;
 }
 
 // ---------------------------------------------------------------------------
 // a6/a7: association (float32 screening, float64 re-scoring) and counts.
-// The float32 unit references are staged in LDS when they fit (the loop over
-// references is uniform, so every read is a broadcast).
+// The reference loop is uniform, so the float32 unit references stream
+// through scalar loads.
 // ---------------------------------------------------------------------------
-constexpr int kAssocLdsFloats = 8192;
-
 template <int M>
 __global__ __launch_bounds__(kNormThreads) void k_associate(
     const float *__restrict__ objs, int64_t N, const int32_t *__restrict__ rank,
@@ -222,42 +247,33 @@ __global__ __launch_bounds__(kNormThreads) void k_associate(
     int32_t *__restrict__ niche, float *__restrict__ dist, double *__restrict__ dist64,
     int32_t *__restrict__ rho, int32_t *__restrict__ bcount, uint8_t *__restrict__ selflag,
     DevScalars *__restrict__ sc) {
-    __shared__ float lr[kAssocLdsFloats];
+    __shared__ int32_t hist[2 * kLdsNicheRefs];
     if (sc->err) return;
-    const bool in_lds = H * M <= kAssocLdsFloats;
-    if (in_lds) {
-        for (int q = threadIdx.x; q < H * M; q += kNormThreads) lr[q] = rhat32[q];
-        __syncthreads();
-    }
-    const float *R = in_lds ? lr : rhat32;
+    const float *__restrict__ R = rhat32;  // uniform reads: scalar loads
     const int32_t l = sc->last_front;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int32_t r = rank[i];
-    if (r > l) {
+    const int32_t r = i < N ? rank[i] : 0x7fffffff;
+    int cls = -1;
+    int32_t best = 0;
+    if (r <= l) {
+        double fp[M];
+        float y[M];
+        const float l1 = normalise_point<M>(objs + i * M, sc->z, sc->a, fp, y);
+        double d1, d2;
+        associate_point<M>(fp, y, l1, R, rhat64, H, best, d1, d2);
+        niche[i] = best;
+        if (dist) dist[i] = (float)d1;
+        dist64[i] = d1;
+        if (near_tie(d1, d2)) atomicAdd(&sc->near_ties, 1);
+        cls = r < l ? 0 : 1;
+        selflag[i] = r < l ? 1 : 0;
+    } else if (i < N) {
         niche[i] = -1;
         if (dist) dist[i] = -1.0f;
         dist64[i] = -1.0;
         selflag[i] = 0;
-        return;
     }
-    double fp[M];
-    float y[M];
-    const float l1 = normalise_point<M>(objs + i * M, sc->z, sc->a, fp, y);
-    int32_t best;
-    double d1, d2;
-    associate_point<M>(fp, y, l1, R, rhat64, H, best, d1, d2);
-    niche[i] = best;
-    if (dist) dist[i] = (float)d1;
-    dist64[i] = d1;
-    if (near_tie(d1, d2)) atomicAdd(&sc->near_ties, 1);
-    if (r < l) {
-        atomicAdd(&rho[best], 1);
-        selflag[i] = 1;
-    } else {
-        atomicAdd(&bcount[best], 1);
-        selflag[i] = 0;
-    }
+    niche_count_block(H, cls, best, rho, bcount, hist);
 }
 
 // ---------------------------------------------------------------------------
@@ -305,6 +321,7 @@ __global__ __launch_bounds__(256) void k_associate_bf16(
     constexpr int KP = M <= 8 ? 8 : 16;
     using Op = BfOperand<KP>;
     constexpr int KL = Op::kPerLane;
+    __shared__ int32_t hist[2 * kLdsNicheRefs];
     if (sc->err) return;
     const int32_t l = sc->last_front;
     const int lane = (int)lane_id();
@@ -383,25 +400,23 @@ __global__ __launch_bounds__(256) void k_associate_bf16(
     } else {
         d2 = fmin(d2, od1);
     }
-    if (!inrange || half != 0) return;
-    if (!active) {
-        niche[i] = -1;
-        if (dist) dist[i] = -1.0f;
-        dist64[i] = -1.0;
-        selflag[i] = 0;
-        return;
+    int cls = -1;
+    if (inrange && half == 0) {
+        if (!active) {
+            niche[i] = -1;
+            if (dist) dist[i] = -1.0f;
+            dist64[i] = -1.0;
+            selflag[i] = 0;
+        } else {
+            niche[i] = best;
+            if (dist) dist[i] = (float)d1;
+            dist64[i] = d1;
+            if (near_tie(d1, d2)) atomicAdd(&sc->near_ties, 1);
+            cls = r < l ? 0 : 1;
+            selflag[i] = r < l ? 1 : 0;
+        }
     }
-    niche[i] = best;
-    if (dist) dist[i] = (float)d1;
-    dist64[i] = d1;
-    if (near_tie(d1, d2)) atomicAdd(&sc->near_ties, 1);
-    if (r < l) {
-        atomicAdd(&rho[best], 1);
-        selflag[i] = 1;
-    } else {
-        atomicAdd(&bcount[best], 1);
-        selflag[i] = 0;
-    }
+    niche_count_block(H, cls, best, rho, bcount, hist);
 }
 
 // ---------------------------------------------------------------------------
@@ -414,6 +429,7 @@ __global__ __launch_bounds__(1024) void k_niche_plan(int H, const int32_t *__res
                                                      const int32_t *__restrict__ bcount,
                                                      int32_t *__restrict__ bstart,
                                                      int32_t *__restrict__ bcursor,
+                                                     int32_t *__restrict__ gstart,
                                                      DevScalars *__restrict__ sc) {
     __shared__ uint32_t lds[17];
     __shared__ int64_t red[16];
@@ -421,7 +437,7 @@ __global__ __launch_bounds__(1024) void k_niche_plan(int H, const int32_t *__res
     if (sc->err) return;
     const int64_t R = sc->num_from_last;
     // bucket starts (exclusive scan of bcount), chunked by blockDim
-    uint32_t run = 0;
+    uint32_t run = 0, grun = 0;
     int64_t vmax = 0;
     for (int base = 0; base < H; base += blockDim.x) {
         const int j = base + threadIdx.x;
@@ -430,12 +446,21 @@ __global__ __launch_bounds__(1024) void k_niche_plan(int H, const int32_t *__res
             const int64_t top = (int64_t)rho[j] + bcount[j];
             vmax = top > vmax ? top : vmax;
         }
-        uint32_t tot;
+        uint32_t tot, gtot;
         const uint32_t ex = block_exclusive_scan(v, lds, &tot);
-        if (j < H) { bstart[j] = (int32_t)(run + ex); bcursor[j] = (int32_t)(run + ex); }
+        const uint32_t gex = block_exclusive_scan((v + kRankGroup - 1) / kRankGroup, lds, &gtot);
+        if (j < H) {
+            bstart[j] = (int32_t)(run + ex);
+            bcursor[j] = (int32_t)(run + ex);
+            gstart[j] = (int32_t)(grun + gex);
+        }
         run += tot;
+        grun += gtot;
     }
-    if (threadIdx.x == 0) bstart[H] = (int32_t)run;
+    if (threadIdx.x == 0) {
+        bstart[H] = (int32_t)run;
+        gstart[H] = (int32_t)grun;
+    }
     vmax = wave_max(vmax);
     if (lane_id() == 0) red[threadIdx.x / kWave] = vmax;
     __syncthreads();
@@ -504,45 +529,69 @@ __global__ __launch_bounds__(1024) void k_niche_plan(int H, const int32_t *__res
 }
 
 // last-front members -> reference buckets (order inside a bucket is arbitrary)
-__global__ __launch_bounds__(256) void k_bucket_scatter(int64_t N, const int32_t *__restrict__ rank,
+__global__ __launch_bounds__(256) void k_bucket_scatter(int64_t N, int H,
+                                                        const int32_t *__restrict__ rank,
                                                         const int32_t *__restrict__ niche,
                                                         const double *__restrict__ dist64,
                                                         int32_t *__restrict__ bcursor,
                                                         double *__restrict__ bd,
                                                         int32_t *__restrict__ bi,
                                                         const DevScalars *__restrict__ sc) {
+    __shared__ int32_t cnt[kLdsNicheRefs];
     if (sc->err) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N || rank[i] != sc->last_front) return;
-    const int32_t slot = atomicAdd(&bcursor[niche[i]], 1);
+    const bool member = i < N && rank[i] == sc->last_front;
+    const int32_t b = member ? niche[i] : 0;
+    const int32_t slot = bucket_slot_block(H, member, b, bcursor, cnt);
+    if (!member) return;
     bd[slot] = dist64[i];
     bi[slot] = (int32_t)i;
 }
 
 // t_i = #members of the same reference with smaller (distance, index); pick
-// when (rho + t, reference) is below the threshold.
-__global__ __launch_bounds__(256) void k_bucket_rank(int64_t nl, const int32_t *__restrict__ niche,
-                                                     const int32_t *__restrict__ rho,
-                                                     const int32_t *__restrict__ bstart,
-                                                     const double *__restrict__ bd,
-                                                     const int32_t *__restrict__ bi,
-                                                     uint8_t *__restrict__ selflag,
-                                                     const DevScalars *__restrict__ sc) {
+// when (rho + t, reference) is below the threshold.  Work-group g ranks
+// kRankGroup members of one bucket (gstart maps groups to buckets) against the
+// whole bucket, staged through LDS.
+__global__ __launch_bounds__(kRankGroup) void k_bucket_rank(int H, const int32_t *__restrict__ rho,
+                                                            const int32_t *__restrict__ bstart,
+                                                            const int32_t *__restrict__ gstart,
+                                                            const double *__restrict__ bd,
+                                                            const int32_t *__restrict__ bi,
+                                                            uint8_t *__restrict__ selflag,
+                                                            const DevScalars *__restrict__ sc) {
+    constexpr int kChunk = 2048;
+    __shared__ double sd[kChunk];
+    __shared__ int32_t si[kChunk];
     if (sc->err) return;
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n_l = sc->last_front_size;
-    if (s >= n_l || s >= nl) return;
-    const double d = bd[s];
-    const int32_t i = bi[s];
-    const int32_t j = niche[i];
-    const int32_t b0 = bstart[j], b1 = bstart[j + 1];
-    int32_t t = 0;
-#pragma unroll 8
-    for (int32_t m = b0; m < b1; ++m) {
-        const double dm = bd[m];
-        const int32_t im = bi[m];
-        t += (dm < d || (dm == d && im < i)) ? 1 : 0;
+    const int32_t g = blockIdx.x;
+    if (g >= gstart[H]) return;
+    int32_t lo = 0, hi = H - 1;  // the bucket j with gstart[j] <= g < gstart[j + 1]
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (gstart[mid] <= g) lo = mid; else hi = mid - 1;
     }
+    const int32_t j = lo;
+    const int32_t b0 = bstart[j], b1 = bstart[j + 1];
+    const int32_t s = b0 + (g - gstart[j]) * kRankGroup + (int32_t)threadIdx.x;
+    const bool mine = s < b1;
+    const double d = mine ? bd[s] : 0.0;
+    const int32_t i = mine ? bi[s] : 0;
+    int32_t t = 0;
+    for (int32_t c0 = b0; c0 < b1; c0 += kChunk) {
+        const int32_t c1 = min(c0 + kChunk, b1);
+        __syncthreads();
+        for (int32_t q = c0 + (int32_t)threadIdx.x; q < c1; q += kRankGroup) {
+            sd[q - c0] = bd[q];
+            si[q - c0] = bi[q];
+        }
+        __syncthreads();
+        if (mine) {
+            const int32_t n = c1 - c0;
+#pragma unroll 8
+            for (int32_t m = 0; m < n; ++m) t += (sd[m] < d || (sd[m] == d && si[m] < i)) ? 1 : 0;
+        }
+    }
+    if (!mine) return;
     const int64_t lev = (int64_t)rho[j] + t;
     const int64_t V = sc->level_V;
     if (lev < V || (lev == V && j < sc->ref_thr)) selflag[i] = 1;
@@ -580,8 +629,18 @@ hipError_t run_select_stage(const SelectViews &v, hipStream_t s) {
     v.mark();
     hipLaunchKernelGGL(k_extreme_partial, dim3(nparts), dim3(kNormThreads), 0, s, v.objs, N, M,
                        v.rank, v.sc, v.p_asf, v.p_idx, v.p_nad);
-    hipLaunchKernelGGL(k_solve, dim3(1), dim3(64), 0, s, v.objs, M, nparts, v.p_asf, v.p_idx,
-                       v.p_nad, v.sc);
+    switch (M) {
+#define NSGA3_CASE(m)                                                                               \
+    case m:                                                                                         \
+        hipLaunchKernelGGL(k_solve<m>, dim3(1), dim3(kSolveThreads), 0, s, v.objs, nparts, v.p_asf, \
+                           v.p_idx, v.p_nad, v.sc);                                                 \
+        break;
+        NSGA3_CASE(2) NSGA3_CASE(3) NSGA3_CASE(4) NSGA3_CASE(5) NSGA3_CASE(6) NSGA3_CASE(7)
+        NSGA3_CASE(8) NSGA3_CASE(9) NSGA3_CASE(10) NSGA3_CASE(11) NSGA3_CASE(12) NSGA3_CASE(13)
+        NSGA3_CASE(14) NSGA3_CASE(15) NSGA3_CASE(16)
+#undef NSGA3_CASE
+        default: return hipErrorInvalidValue;
+    }
     const unsigned nbN = (unsigned)((N + 255) / 256);
     v.mark();
     const unsigned nbW = (unsigned)((N + 127) / 128);  // 32 points per wave, 4 waves per block
@@ -605,11 +664,13 @@ hipError_t run_select_stage(const SelectViews &v, hipStream_t s) {
     }
     v.mark();
     hipLaunchKernelGGL(k_niche_plan, dim3(1), dim3(1024), 0, s, v.H, v.rho, v.bcount, v.bstart,
-                       v.bcursor, v.sc);
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(nbN), dim3(256), 0, s, N, v.rank, v.niche, v.dist64,
+                       v.bcursor, v.gstart, v.sc);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(nbN), dim3(256), 0, s, N, v.H, v.rank, v.niche, v.dist64,
                        v.bcursor, v.bd, v.bi, v.sc);
-    hipLaunchKernelGGL(k_bucket_rank, dim3(nbN), dim3(256), 0, s, N, v.niche, v.rho, v.bstart, v.bd,
-                       v.bi, v.selflag, v.sc);
+    // at most ceil(|F_l| / kRankGroup) + H groups, |F_l| <= N
+    const unsigned nbG = (unsigned)((N + kRankGroup - 1) / kRankGroup + v.H);
+    hipLaunchKernelGGL(k_bucket_rank, dim3(nbG), dim3(kRankGroup), 0, s, v.H, v.rho, v.bstart,
+                       v.gstart, v.bd, v.bi, v.selflag, v.sc);
     compact_flags(v.selflag, N, v.selected, v.K, v.temp, &v.sc->n_selected, s);
     if (v.info) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, v.info, v.K, v.sc);
     v.mark();

@@ -120,6 +120,14 @@ def test_engine_edge_instances():
     a = np.arange(600, dtype=np.float32)
     chain = np.stack([a, a], axis=1)  # a total order: 600 fronts
     cases.append((chain, workloads.das_dennis(2, 5).astype(np.float32), 300))
+    # intercept fallbacks: equal objectives (singular), a constant objective (zero nadir)
+    for col in (2, 0):
+        f = rng.uniform(0, 1, (900, 3)).astype(np.float32)
+        if col == 2:
+            f[:, 2] = f[:, 1]
+        else:
+            f[:, 0] = 0.25
+        cases.append((f, workloads.das_dennis(3, 6).astype(np.float32), 450))
     probs = [(torch.from_numpy(np.ascontiguousarray(f)).cuda(),
               torch.from_numpy(np.ascontiguousarray(r)).cuda(), K) for (f, r, K) in cases]
     plan = nsga3.Plan(probs)

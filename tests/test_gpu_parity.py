@@ -105,6 +105,27 @@ def test_objective_counts(M):
     _zero(compare_full(F, R, 700, g))
 
 
+def _fallback_inputs(kind, N=900, seed=7):
+    """Inputs whose intercepts take each fallback of the a5 solve: two equal
+    objectives give two equal extreme rows (singular hyperplane, nadir used);
+    a constant objective also gives a zero nadir entry (replaced by 1)."""
+    rng = np.random.default_rng(seed)
+    F = rng.uniform(0, 1, (N, 3)).astype(np.float32)
+    if kind == "equal_objectives":
+        F[:, 2] = F[:, 1]
+    else:
+        F[:, 0] = 0.25
+    return F, workloads.das_dennis(3, 6).astype(np.float32)
+
+
+@pytest.mark.parametrize("kind,code", [("equal_objectives", 1), ("constant_objective", 2)])
+def test_intercept_fallbacks(kind, code):
+    F, R = _fallback_inputs(kind)
+    g = gpu_select(F, R, F.shape[0] // 2)
+    assert g["info"].intercept_fallback == code
+    _zero(compare_full(F, R, F.shape[0] // 2, g))
+
+
 def test_negative_and_signed_zero_objectives():
     w = workloads.make("ties", N=2000, seed=9)
     F = w.objs.copy() - np.float32(0.75)
