@@ -567,13 +567,15 @@ __device__ void item_peel_tail(const EInst &I, int32_t k, uint32_t *smem) {
 }
 
 // a2 for two objectives: the points are in lexicographic (key_1, key_2)
-// order, so every earlier point has key_1 <= the current one and a front
-// dominates the current point p iff its smallest key_2 so far is <= p's
-// (equality means an identical point, which is always p's predecessor, and
-// identical points share a rank).  The smallest key_2 per front, T2, never
-// decreases with the front index, so p's rank is the number of fronts with
-// T2 <= key_2(p), found by a two-level lane-parallel count, and p lowers T2
-// of its front.  One wave, one ordered pass; ranks equal the peeling levels.
+// order, so every earlier point has key_1 <= the current one, and an earlier
+// point dominates the current point p iff its key_2 is <= p's and it is not
+// identical to p (identical points are adjacent and share a rank).  The rank is
+// one more than the largest rank among p's dominators.  T2[r], the smallest
+// key_2 among points of rank r so far, never decreases with r, so the
+// dominators before a batch of 64 points contribute #{r : T2[r] <= key_2(p)}
+// (a binary search per lane); dominators inside the batch are folded in order,
+// one broadcast per point.  The batch then lowers T2 of its ranks.  One wave,
+// one ordered pass; ranks equal the peeling levels.
 template <int M>
 __device__ void item_rank2(const EInst &I, uint32_t *smem) {
     if constexpr (M != 2) return;  // only two-objective instances take this stage
@@ -590,49 +592,47 @@ __device__ void item_rank2(const EInst &I, uint32_t *smem) {
     const int lane = (int)lane_id();
     int32_t nf = 0;
     bool overflow = false;
-    uint32_t pa = 0, pb = 0;
+    uint32_t pa = 0, pb = 0;  // last point of the previous batch and its rank
     int32_t prank = -1;
-    for (int32_t base = 0; base < N && !overflow; base += kWave) {
+    for (int32_t base = 0; base < N; base += kWave) {
         const int32_t p = base + lane;
-        uint32_t a = 0, b = 0;
-        if (p < N) {
-            a = recs[(size_t)p * 4];
-            b = recs[(size_t)p * 4 + 1];
+        const bool valid = p < N;
+        const uint32_t a = valid ? recs[(size_t)p * 4] : 0xffffffffu;
+        const uint32_t b = valid ? recs[(size_t)p * 4 + 1] : 0xffffffffu;
+        // earlier batches: number of fronts with T2 <= b (T2 is non-decreasing)
+        int32_t lo = 0, hi = nf;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (T2[mid] <= b) lo = mid + 1; else hi = mid;
         }
+        int32_t r = lo;
+        // a run of points identical to the previous batch's last one keeps its rank
+        if (prank >= 0 && a == pa && b == pb) r = prank;
+        // earlier points of this batch, in order (point s is final when folded)
         const int32_t n_here = min(kWave, N - base);
-        int32_t myrank = 0;
-        for (int32_t t = 0; t < n_here; ++t) {
-            const uint32_t ka = __shfl(a, t, 64), kb = __shfl(b, t, 64);
-            int32_t r;
-            if (prank >= 0 && ka == pa && kb == pb) {
-                r = prank;
-            } else if (nf <= kWave) {
-                const bool dom = lane < nf && T2[lane] <= kb;
-                r = (int32_t)__popcll(ballot(dom));
-            } else {
-                const int32_t s = (nf + kWave - 1) / kWave;  // sample stride
-                const int32_t q = lane * s;
-                const int32_t c1 = (int32_t)__popcll(ballot(q < nf && T2[q] <= kb));
-                const int32_t lo = c1 == 0 ? 0 : (c1 - 1) * s + 1;
-                const int32_t hi = c1 == 0 ? 0 : min(c1 * s, nf);
-                const int32_t q2 = lo + lane;
-                r = lo + (int32_t)__popcll(ballot(q2 < hi && T2[q2] <= kb));
-            }
-            if (r == nf) {
-                if (nf == CAP) { overflow = true; break; }
-                if (lane == 0) cnt[nf] = 0;
-                ++nf;
-            }
-            if (lane == 0) {
-                T2[r] = kb;
-                cnt[r] += 1;
-            }
-            if (lane == t) myrank = r;
-            pa = ka;
-            pb = kb;
-            prank = r;
+        for (int32_t s = 0; s < n_here; ++s) {
+            const int32_t rs = __builtin_amdgcn_readlane(r, s);
+            const uint32_t as = __builtin_amdgcn_readlane(a, s);
+            const uint32_t bs = __builtin_amdgcn_readlane(b, s);
+            if (lane > s && bs <= b && !(as == a && bs == b)) r = max(r, rs + 1);
         }
-        if (!overflow && p < N) rank_s[p] = myrank;
+        int32_t top = valid ? r + 1 : 0;
+        for (int o = 32; o > 0; o >>= 1) top = max(top, __shfl_xor(top, o, 64));
+        if (top > CAP) { overflow = true; break; }
+        for (int32_t q = nf + lane; q < top; q += kWave) {
+            T2[q] = 0xffffffffu;
+            cnt[q] = 0u;
+        }
+        nf = max(nf, top);
+        if (valid) {
+            atomicMin(&T2[r], b);
+            atomicAdd(&cnt[r], 1u);
+            rank_s[p] = r;
+        }
+        const int32_t last = n_here - 1;
+        pa = __builtin_amdgcn_readlane(a, last);
+        pb = __builtin_amdgcn_readlane(b, last);
+        prank = __builtin_amdgcn_readlane(r, last);
     }
     int32_t *fsize = at<int32_t>(w, L.fsize);
     if (!overflow)

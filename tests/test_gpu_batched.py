@@ -120,6 +120,14 @@ def test_engine_edge_instances():
     a = np.arange(600, dtype=np.float32)
     chain = np.stack([a, a], axis=1)  # a total order: 600 fronts
     cases.append((chain, workloads.das_dennis(2, 5).astype(np.float32), 300))
+    # M = 2 ranking pass: runs of identical points across 64-point batches, and
+    # more fronts than its table holds (7000 > 6144: the level peel takes over)
+    a3 = np.repeat(np.arange(700, dtype=np.float32), 3)
+    cases.append((np.stack([a3, a3], axis=1), workloads.das_dennis(2, 5).astype(np.float32), 1000))
+    g2 = rng.integers(0, 40, size=(3000, 2)).astype(np.float32)
+    cases.append((g2, workloads.das_dennis(2, 5).astype(np.float32), 1500))
+    a7 = np.arange(7000, dtype=np.float32)
+    cases.append((np.stack([a7, a7], axis=1), workloads.das_dennis(2, 5).astype(np.float32), 3500))
     # intercept fallbacks: equal objectives (singular), a constant objective (zero nadir)
     for col in (2, 0):
         f = rng.uniform(0, 1, (900, 3)).astype(np.float32)
