@@ -184,8 +184,8 @@ void nsga3_plan_destroy(nsga3_plan *plan);
 
 /* Work-item shapes the autotuner chose so far in this context, 5 int32 per
  * entry: M, N range (0: N < 2048, 1: < 8192, 2: < 32768, 3: larger), phase-A
- * items per level, longest remaining list peeled in one item (0: never), and
- * largest front for that.  Writes at most `cap` entries to out (host) and the
+ * items per level (pairwise decrements only), longest remaining list peeled in
+ * one item (0: never), and largest front for that.  Writes at most `cap` entries to out (host) and the
  * number of entries to *count (host). */
 nsga3_status nsga3_tuned_shapes(const nsga3_ctx *ctx, int32_t *out, int32_t cap, int32_t *count);
 
@@ -195,8 +195,9 @@ nsga3_status nsga3_tuned_shapes(const nsga3_ctx *ctx, int32_t *out, int32_t cap,
  *   8 outputs in original order, 9 extreme points, 10 association,
  *   11 bucket scatter, 12 niche picks, 13 compaction counts, 14 compaction
  *   writes, 15 short-list split in one item, 16 remaining levels in one item,
- *   17 two-objective ranks in one ordered pass, 18 done. */
-#define NSGA3_PLAN_STAGES 19
+ *   17 two-objective ranks in one ordered pass, 18 block tables of a front,
+ *   19 done. */
+#define NSGA3_PLAN_STAGES 20
 
 /* Diagnostics of a plan created while profiling was enabled: per stage, the
  * block-milliseconds spent inside its work items and its epilogues, and the

@@ -45,7 +45,7 @@ class _Options(ctypes.Structure):
 PLAN_STAGES = ("keys_refs", "radix_hist", "radix_scatter", "records", "dominance",
                "split_count", "split_write", "peel_decrements", "orig_order", "extremes",
                "association", "bucket_scatter", "niche_picks", "compact_count", "compact_write",
-               "split_one", "peel_tail", "rank_2d", "done")
+               "split_one", "peel_tail", "rank_2d", "front_tables", "done")
 
 
 class _Problem(ctypes.Structure):

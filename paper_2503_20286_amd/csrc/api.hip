@@ -583,6 +583,8 @@ static nsga3_status tune_group(nsga3_ctx *ctx, const std::vector<nsga3::EInst> &
     std::vector<EInst> cand(group);
     for (const EngineShape &sh : kShapeCandidates) {
         if (st != NSGA3_OK) break;
+        // phase-A items per level only shape the pairwise decrements
+        if (group[0].bit_peel && sh.pa_items != kShapeDefault.pa_items) continue;
         for (EInst &e : cand) {
             e.pa_items = sh.pa_items;
             e.tail_max = sh.tail_max;
@@ -663,6 +665,7 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
         const int v = atoi(e);
         if (v >= 0) base.tail_front = v;
     }
+    pl->bitdom = !(getenv("NSGA3_PAIRWISE") && atoi(getenv("NSGA3_PAIRWISE")) != 0);
     std::vector<std::pair<int32_t, int32_t>> cls;  // (first instance, count) per M
     for (int32_t q = 0; q < B; ++q) {
         const nsga3_problem &p = probs[order[q]];
@@ -684,6 +687,7 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
         e.pa_items = base.pa_items;
         e.tail_max = base.tail_max;
         e.tail_front = base.tail_front;
+        e.bit_peel = pl->bitdom ? 1 : 0;
         e.L = elayout(p.N, p.M, p.H);
         if (q == 0 || p.M != probs[order[q - 1]].M) cls.push_back({q, 0});
         cls.back().second++;
@@ -715,7 +719,6 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
     }
     boff[nclass] = (int64_t)bmap.size();
     coff[nclass] = (int64_t)cmap.size();
-    pl->bitdom = !(getenv("NSGA3_PAIRWISE") && atoi(getenv("NSGA3_PAIRWISE")) != 0);
     if (hipMalloc((void **)&pl->d_glob, sizeof(EGlobal) * (size_t)(2 * nclass)) != hipSuccess ||
         hipMalloc((void **)&pl->d_map, sizeof(int2) * (map.size() ? map.size() : 1)) != hipSuccess) {
         (void)hipGetLastError();

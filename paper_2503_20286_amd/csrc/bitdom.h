@@ -8,6 +8,7 @@
 #pragma once
 
 #include "common.h"
+#include "prims.h"
 
 namespace nsga3 {
 
@@ -95,6 +96,207 @@ __device__ __forceinline__ void count_many64(const uint32_t *const (&S)[R], cons
 
 __device__ __forceinline__ uint64_t low_bits(uint32_t c) {
     return c >= 64u ? ~0ull : ((1ull << c) - 1ull);
+}
+
+// ---------------------------------------------------------------------------
+// Device bodies shared by the single-selection kernels (bitdom.hip) and the
+// batched engine (engine.hip).
+// ---------------------------------------------------------------------------
+constexpr int kFwdThreads = 256;
+constexpr int kTJ = 2;                            // points per lane
+constexpr int kTileJ = kFwdThreads * kTJ;         // points per work item
+constexpr int kLdsTabDwords = 8704;               // 34 KiB of tables per work item
+
+template <int M>
+__host__ __device__ constexpr int blocks_per_chunk() {
+    return kLdsTabDwords / blk_stride(M) < 1 ? 1 : kLdsTabDwords / blk_stride(M);
+}
+
+// ---------------------------------------------------------------------------
+// Tables: one wave per block of 64 consecutive list entries.
+// ---------------------------------------------------------------------------
+template <bool kWaveSync>
+__device__ __forceinline__ void block_sync() {
+    if constexpr (kWaveSync) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// kWaveSync: the calling wave builds its block alone (work-groups of several
+// waves, each with its own inv[64]); otherwise the work-group is this one wave.
+template <int M, bool kWaveSync = false>
+__device__ __forceinline__ void build_block(const uint32_t *__restrict__ rec, int32_t n,
+                                            uint32_t *__restrict__ tabs, int32_t b, int32_t *inv) {
+    constexpr int MP = rec_stride(M);
+    constexpr int TS = blk_stride(M);
+    if ((int64_t)b * kBlk >= n) return;
+    const int l = (int)lane_id();
+    const int32_t e = b * kBlk + l;
+    const bool valid = e < n;
+    const int32_t nmem = min(kBlk, n - b * kBlk);
+    uint32_t *T = tabs + (size_t)b * TS;
+    const int32_t pos = valid ? (int32_t)rec[(size_t)e * MP + M] : 0x7fffffff;
+    T[blk_pos_off() + l] = (uint32_t)pos;
+    // (no uniform-address loads: a persistent caller's records change between
+    // stages, and a scalar load could hit a stale scalar-cache line)
+    const int32_t last = __shfl(pos, nmem - 1, 64);
+    if (l == 0) {
+        T[0] = (uint32_t)pos;
+        T[1] = (uint32_t)last;
+        T[2] = (uint32_t)nmem;
+        T[3] = 0;
+    }
+    for (int k = 0; k < M; ++k) {
+        const uint32_t key = valid ? rec[(size_t)e * MP + k] : 0xffffffffu;
+        uint32_t rank = 0;
+        for (int m = 0; m < kBlk; ++m) {
+            const uint32_t o = __shfl(key, m, 64);
+            rank += (o < key || (o == key && m < l)) ? 1u : 0u;
+        }
+        T[blk_key_off(k) + rank] = key;
+        inv[rank] = l;
+        block_sync<kWaveSync>();
+        const int mem = inv[l];
+        uint64_t bit = (mem < nmem) ? (1ull << mem) : 0ull;
+        for (int o = 1; o < kBlk; o <<= 1) {
+            const uint64_t t = __shfl_up(bit, o, 64);
+            if (l >= o) bit |= t;
+        }
+        uint32_t *pm = T + blk_pm_off(M, k);
+        pm[l + 1] = (uint32_t)bit;
+        pm[65 + l + 1] = (uint32_t)(bit >> 32);
+        if (l == 0) {
+            pm[0] = 0u;
+            pm[65] = 0u;
+        }
+        block_sync<kWaveSync>();
+    }
+}
+
+// Stage `nb` consecutive tables into LDS.
+template <int M>
+__device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__restrict__ tabs,
+                                             int32_t b0, int32_t nb) {
+    constexpr int TS = blk_stride(M);
+    const uint4 *src = reinterpret_cast<const uint4 *>(tabs + (size_t)b0 * TS);
+    uint4 *dst = reinterpret_cast<uint4 *>(lds);
+    const int nvec = nb * (TS / 4);
+    for (int q = threadIdx.x; q < nvec; q += kFwdThreads) dst[q] = src[q];
+}
+
+// Forward: for each of the wave's kTJ x 64 points j (keys kj, run starts run),
+// add the number of members of the staged blocks that dominate j.
+template <int M>
+__device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32_t run_lo,
+                                           int32_t run_hi, const uint32_t (&kj)[kTJ][M],
+                                           const int32_t (&run)[kTJ], int32_t (&cnt)[kTJ]) {
+    constexpr int TS = blk_stride(M);
+    for (int32_t b = 0; b < nb; ++b) {
+        const uint32_t *T = lt + b * TS;
+        const int32_t bmin = (int32_t)T[0];
+        const int32_t bmax = (int32_t)T[1];
+        if (bmin >= run_hi) break;  // later blocks start later still
+        const bool full = bmax < run_lo;
+        // the kTJ x M key searches in lockstep
+        const uint32_t *S[kTJ * M];
+        uint32_t x[kTJ * M], c[kTJ * M];
+#pragma unroll
+        for (int t = 0; t < kTJ; ++t)
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                S[t * M + k] = T + blk_key_off(k);
+                x[t * M + k] = kj[t][k];
+            }
+        count_many64<kTJ * M, true>(S, x, c);
+#pragma unroll
+        for (int t = 0; t < kTJ; ++t) {
+            uint64_t m = ~0ull;
+            if (!full) {
+                if (run[t] <= bmin) m = 0ull;
+                else if (run[t] <= bmax)
+                    m = low_bits(count_pos_lt64(reinterpret_cast<const int32_t *>(T + blk_pos_off()),
+                                                run[t]));
+            }
+#pragma unroll
+            for (int k = 0; k < M; ++k) m &= prefix_mask(T + blk_pm_off(M, k), c[t * M + k]);
+            cnt[t] += __popcll(m);
+        }
+    }
+}
+
+// Loads the wave's points (records with MP stride, run starts) into registers.
+template <int M>
+__device__ __forceinline__ void load_points(const uint32_t *__restrict__ jrec,
+                                            const int32_t *__restrict__ jrun, int32_t nj,
+                                            int32_t jbase, int lane, uint32_t (&kj)[kTJ][M],
+                                            int32_t (&run)[kTJ]) {
+    constexpr int MP = rec_stride(M);
+#pragma unroll
+    for (int t = 0; t < kTJ; ++t) {
+        const int32_t q = jbase + t * kWave + lane;
+        if (q < nj) {
+#pragma unroll
+            for (int k = 0; k < M; ++k) kj[t][k] = jrec[(size_t)q * MP + k];
+            run[t] = jrun[q];
+        } else {
+#pragma unroll
+            for (int k = 0; k < M; ++k) kj[t][k] = 0u;  // below every key: dominated by nothing
+            run[t] = 0;
+        }
+    }
+}
+
+
+// Uniform reads of lists that other work-groups of a persistent launch may
+// have written: a workgroup-scope atomic load is a vector load (never served by
+// the scalar cache, which vector stores do not update).
+template <typename T>
+__device__ __forceinline__ T vld(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One item of a peeling level (Eq. (9)): the front blocks [b0, b0 + nb) (one
+// chunk, staged in lt) against T consecutive tiles of the remaining list from
+// tile jt0; every remaining point's count drops by the chunk members that
+// dominate it.  The whole work-group (kFwdThreads) calls it with uniform
+// arguments; it returns early, before any barrier, when every chunk member
+// lies at or after the tiles' last run start.
+template <int M, int T>
+__device__ __forceinline__ void fwd_level_item(const uint32_t *__restrict__ tabs, int32_t b0,
+                                               int32_t nb, const uint32_t *__restrict__ uk,
+                                               const int32_t *__restrict__ urun, int32_t nu,
+                                               int32_t *__restrict__ ucnt, int32_t jt0,
+                                               uint32_t *lt) {
+    constexpr int TS = blk_stride(M);
+    if (jt0 * kTileJ >= nu) return;
+    const int32_t tile_last = min((jt0 + T) * kTileJ, nu) - 1;
+    if ((int32_t)vld(&tabs[(size_t)b0 * TS]) >= vld(&urun[tile_last])) return;
+    stage_tables<M>(lt, tabs, b0, nb);
+    __syncthreads();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = (int)lane_id();
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int32_t jbase = (jt0 + t) * kTileJ + w * kWave * kTJ;
+        if (jbase >= nu) break;
+        uint32_t kj[kTJ][M];
+        int32_t run[kTJ], cnt[kTJ];
+        load_points<M>(uk, urun, nu, jbase, lane, kj, run);
+#pragma unroll
+        for (int u = 0; u < kTJ; ++u) cnt[u] = 0;
+        const int32_t run_lo = vld(&urun[jbase]);
+        const int32_t run_hi = vld(&urun[min(jbase + kWave * kTJ - 1, nu - 1)]);
+        fwd_blocks<M>(lt, nb, run_lo, run_hi, kj, run, cnt);
+#pragma unroll
+        for (int u = 0; u < kTJ; ++u) {
+            const int32_t q = jbase + u * kWave + lane;
+            if (q < nu && cnt[u]) atomicSub(&ucnt[q], cnt[u]);
+        }
+    }
 }
 
 }  // namespace nsga3

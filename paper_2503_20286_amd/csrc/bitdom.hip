@@ -15,65 +15,6 @@
 
 namespace nsga3 {
 
-constexpr int kFwdThreads = 256;
-constexpr int kTJ = 2;                            // points per lane
-constexpr int kTileJ = kFwdThreads * kTJ;         // points per work item
-constexpr int kLdsTabDwords = 8704;               // 34 KiB of tables per work item
-
-template <int M>
-__host__ __device__ constexpr int blocks_per_chunk() {
-    return kLdsTabDwords / blk_stride(M) < 1 ? 1 : kLdsTabDwords / blk_stride(M);
-}
-
-// ---------------------------------------------------------------------------
-// Tables: one wave per block of 64 consecutive list entries.
-// ---------------------------------------------------------------------------
-template <int M>
-__device__ __forceinline__ void build_block(const uint32_t *__restrict__ rec, int32_t n,
-                                            uint32_t *__restrict__ tabs, int32_t b, int32_t *inv) {
-    constexpr int MP = rec_stride(M);
-    constexpr int TS = blk_stride(M);
-    if ((int64_t)b * kBlk >= n) return;
-    const int l = threadIdx.x;
-    const int32_t e = b * kBlk + l;
-    const bool valid = e < n;
-    const int32_t nmem = min(kBlk, n - b * kBlk);
-    uint32_t *T = tabs + (size_t)b * TS;
-    const int32_t pos = valid ? (int32_t)rec[(size_t)e * MP + M] : 0x7fffffff;
-    T[blk_pos_off() + l] = (uint32_t)pos;
-    if (l == 0) {
-        T[0] = (uint32_t)pos;
-        T[1] = rec[(size_t)(b * kBlk + nmem - 1) * MP + M];
-        T[2] = (uint32_t)nmem;
-        T[3] = 0;
-    }
-    for (int k = 0; k < M; ++k) {
-        const uint32_t key = valid ? rec[(size_t)e * MP + k] : 0xffffffffu;
-        uint32_t rank = 0;
-        for (int m = 0; m < kBlk; ++m) {
-            const uint32_t o = __shfl(key, m, 64);
-            rank += (o < key || (o == key && m < l)) ? 1u : 0u;
-        }
-        T[blk_key_off(k) + rank] = key;
-        inv[rank] = l;
-        __syncthreads();
-        const int mem = inv[l];
-        uint64_t bit = (mem < nmem) ? (1ull << mem) : 0ull;
-        for (int o = 1; o < kBlk; o <<= 1) {
-            const uint64_t t = __shfl_up(bit, o, 64);
-            if (l >= o) bit |= t;
-        }
-        uint32_t *pm = T + blk_pm_off(M, k);
-        pm[l + 1] = (uint32_t)bit;
-        pm[65 + l + 1] = (uint32_t)(bit >> 32);
-        if (l == 0) {
-            pm[0] = 0u;
-            pm[65] = 0u;
-        }
-        __syncthreads();
-    }
-}
-
 template <int M>
 __global__ __launch_bounds__(64) void k_build_blocks(const uint32_t *__restrict__ rec,
                                                      int32_t n_static,
@@ -84,79 +25,6 @@ __global__ __launch_bounds__(64) void k_build_blocks(const uint32_t *__restrict_
     if (sc->err) return;
     const int32_t n = n_static >= 0 ? n_static : *n_dev;
     build_block<M>(rec, n, tabs, (int32_t)blockIdx.x, inv);
-}
-
-// Stage `nb` consecutive tables into LDS.
-template <int M>
-__device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__restrict__ tabs,
-                                             int32_t b0, int32_t nb) {
-    constexpr int TS = blk_stride(M);
-    const uint4 *src = reinterpret_cast<const uint4 *>(tabs + (size_t)b0 * TS);
-    uint4 *dst = reinterpret_cast<uint4 *>(lds);
-    const int nvec = nb * (TS / 4);
-    for (int q = threadIdx.x; q < nvec; q += kFwdThreads) dst[q] = src[q];
-}
-
-// Forward: for each of the wave's kTJ x 64 points j (keys kj, run starts run),
-// add the number of members of the staged blocks that dominate j.
-template <int M>
-__device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32_t run_lo,
-                                           int32_t run_hi, const uint32_t (&kj)[kTJ][M],
-                                           const int32_t (&run)[kTJ], int32_t (&cnt)[kTJ]) {
-    constexpr int TS = blk_stride(M);
-    for (int32_t b = 0; b < nb; ++b) {
-        const uint32_t *T = lt + b * TS;
-        const int32_t bmin = (int32_t)T[0];
-        const int32_t bmax = (int32_t)T[1];
-        if (bmin >= run_hi) break;  // later blocks start later still
-        const bool full = bmax < run_lo;
-        // the kTJ x M key searches in lockstep
-        const uint32_t *S[kTJ * M];
-        uint32_t x[kTJ * M], c[kTJ * M];
-#pragma unroll
-        for (int t = 0; t < kTJ; ++t)
-#pragma unroll
-            for (int k = 0; k < M; ++k) {
-                S[t * M + k] = T + blk_key_off(k);
-                x[t * M + k] = kj[t][k];
-            }
-        count_many64<kTJ * M, true>(S, x, c);
-#pragma unroll
-        for (int t = 0; t < kTJ; ++t) {
-            uint64_t m = ~0ull;
-            if (!full) {
-                if (run[t] <= bmin) m = 0ull;
-                else if (run[t] <= bmax)
-                    m = low_bits(count_pos_lt64(reinterpret_cast<const int32_t *>(T + blk_pos_off()),
-                                                run[t]));
-            }
-#pragma unroll
-            for (int k = 0; k < M; ++k) m &= prefix_mask(T + blk_pm_off(M, k), c[t * M + k]);
-            cnt[t] += __popcll(m);
-        }
-    }
-}
-
-// Loads the wave's points (records with MP stride, run starts) into registers.
-template <int M>
-__device__ __forceinline__ void load_points(const uint32_t *__restrict__ jrec,
-                                            const int32_t *__restrict__ jrun, int32_t nj,
-                                            int32_t jbase, int lane, uint32_t (&kj)[kTJ][M],
-                                            int32_t (&run)[kTJ]) {
-    constexpr int MP = rec_stride(M);
-#pragma unroll
-    for (int t = 0; t < kTJ; ++t) {
-        const int32_t q = jbase + t * kWave + lane;
-        if (q < nj) {
-#pragma unroll
-            for (int k = 0; k < M; ++k) kj[t][k] = jrec[(size_t)q * MP + k];
-            run[t] = jrun[q];
-        } else {
-#pragma unroll
-            for (int k = 0; k < M; ++k) kj[t][k] = 0u;  // below every key: dominated by nothing
-            run[t] = 0;
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -257,37 +125,12 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
     const int32_t nIC = (nblk + CB - 1) / CB;
     const int32_t nJT = (nu + kTileJ - 1) / kTileJ;
     const int64_t nitems = (int64_t)nIC * nJT;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int lane = (int)lane_id();
     int64_t item = blockIdx.x;
     while (item < nitems) {
         const int32_t ic = (int32_t)(item / nJT);
         const int32_t jt = (int32_t)(item % nJT);
         const int32_t b0 = ic * CB;
-        const int32_t nb = min(CB, nblk - b0);
-        const int32_t tile0 = jt * kTileJ;
-        const int32_t tile_last = min(tile0 + kTileJ - 1, nu - 1);
-        if ((int32_t)tabs[(size_t)b0 * TS] < urun[tile_last]) {  // block-uniform
-            stage_tables<M>(lt, tabs, b0, nb);
-            __syncthreads();
-            const int32_t jbase = tile0 + w * kWave * kTJ;
-            if (jbase < nu) {
-                uint32_t kj[kTJ][M];
-                int32_t run[kTJ], cnt[kTJ];
-                load_points<M>(uk, urun, nu, jbase, lane, kj, run);
-#pragma unroll
-                for (int t = 0; t < kTJ; ++t) cnt[t] = 0;
-                const int32_t run_lo = __builtin_amdgcn_readfirstlane(urun[jbase]);
-                const int32_t run_hi =
-                    __builtin_amdgcn_readfirstlane(urun[min(jbase + kWave * kTJ - 1, nu - 1)]);
-                fwd_blocks<M>(lt, nb, run_lo, run_hi, kj, run, cnt);
-#pragma unroll
-                for (int t = 0; t < kTJ; ++t) {
-                    const int32_t q = jbase + t * kWave + lane;
-                    if (q < nu && cnt[t]) atomicSub(&ucnt[q], cnt[t]);
-                }
-            }
-        }
+        fwd_level_item<M, 1>(tabs, b0, min(CB, nblk - b0), uk, urun, nu, ucnt, jt, lt);
         if (threadIdx.x == 0) s_item = (int32_t)(gridDim.x + atomicAdd(&work[level], 1u));
         __syncthreads();  // every wave is done with lt
         item = s_item;

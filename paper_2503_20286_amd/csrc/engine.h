@@ -43,6 +43,7 @@ enum EStage : int32_t {
     kSSplit1,     // level split of a short list in one item (arg = level)
     kSPeelTail,   // every remaining level in one item (arg = level already split)
     kSRank2,      // M = 2: every rank in one ordered pass (one item)
+    kSBuildF,     // block tables of the front F_k (arg = level)
     kSDone,
 };
 
@@ -136,9 +137,10 @@ struct EInst {
     char *ws;
     int64_t K;
     int32_t N, M, H;
-    int32_t pa_items;   // phase-A items a level aims for (chunk size adapts)
+    int32_t pa_items;   // pairwise phase-A items a level aims for (chunk size adapts)
     int32_t tail_max;   // remaining lists up to this length peel in one item (0: never) ...
     int32_t tail_front; // ... when the current front has at most this many points
+    int32_t bit_peel;   // 1: front x remaining decrements by block bitsets (else pairwise)
     ELayout L;          // elayout(N, M, H)
 };
 

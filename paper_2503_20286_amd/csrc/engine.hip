@@ -25,6 +25,7 @@
 // identical to a single nsga3_select call on the same instance.
 #include <float.h>
 
+#include "bitdom.h"
 #include "engine.h"
 #include "prims.h"
 #include "stage_math.h"
@@ -695,6 +696,43 @@ __device__ void item_phase_a(const EInst &I, int32_t k, int32_t IC, int32_t nJT,
     }
 }
 
+// a2, block-bitset form: tables of the front F_k, one block of 64 entries per
+// wave (the tables of the dominance counts are free again by now).
+template <int M>
+__device__ void item_build_f(const EInst &I, int32_t k, int32_t t, uint32_t *smem) {
+    const ELayout &L = I.L;
+    char *w = I.ws;
+    const int32_t nf = ld(&at<int32_t>(w, L.fsize)[k]);
+    const uint32_t *fk = at<uint32_t>(w, (k & 1) ? L.fk1 : L.fk0);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    build_block<M, true>(fk, nf, at<uint32_t>(w, L.tabs), t * (kEThreads / kWave) + wv,
+                         reinterpret_cast<int32_t *>(smem) + wv * kBlk);
+}
+
+// a2, block-bitset form: one (chunk of front blocks, group of remaining
+// tiles) item of level k; p1 = tile groups.
+constexpr int kLevelTiles = 2;  // remaining-list tiles per item
+static_assert(kEThreads == kFwdThreads, "engine work-groups run the bitset bodies");
+
+template <int M>
+__device__ void item_phase_a_bits(const EInst &I, int32_t k, int32_t ngroups, int32_t t,
+                                  uint32_t *smem) {
+    constexpr int CB = blocks_per_chunk<M>();
+    static_assert(CB * blk_stride(M) <= kESmem, "a chunk of tables fits the worker's LDS");
+    const ELayout &L = I.L;
+    char *w = I.ws;
+    const int32_t nf = ld(&at<int32_t>(w, L.fsize)[k]);
+    const int32_t nu = ld(&at<int32_t>(w, L.usize)[k]);
+    const bool odd = (k & 1) != 0;
+    const int32_t nblk = (int32_t)cdiv(nf, kBlk);
+    const int32_t ic = t / ngroups, jg = t % ngroups;
+    const int32_t b0 = ic * CB;
+    fwd_level_item<M, kLevelTiles>(at<const uint32_t>(w, L.tabs), b0, min(CB, nblk - b0),
+                                   at<const uint32_t>(w, odd ? L.uk1 : L.uk0),
+                                   at<const int32_t>(w, odd ? L.urun1 : L.urun0), nu,
+                                   at<int32_t>(w, odd ? L.ucnt1 : L.ucnt0), jg * kLevelTiles, smem);
+}
+
 // Ranks and counts back to the original order.
 __device__ void item_orig(const EInst &I, int32_t t) {
     const ELayout &L = I.L;
@@ -968,7 +1006,11 @@ __device__ void run_item(const EInst &I, int32_t stage, int32_t arg, int32_t n,
         case kSSplit1: item_split1<M>(I, arg, n, smem); break;
         case kSPeelTail: item_peel_tail<M>(I, arg, smem); break;
         case kSRank2: item_rank2<M>(I, smem); break;
-        case kSPhaseA: item_phase_a<M>(I, arg, p0, p1, t, smem); break;
+        case kSPhaseA:
+            if (I.bit_peel) item_phase_a_bits<M>(I, arg, p1, t, smem);
+            else item_phase_a<M>(I, arg, p0, p1, t, smem);
+            break;
+        case kSBuildF: item_build_f<M>(I, arg, t, smem); break;
         case kSOrig: item_orig(I, t); break;
         case kSExt: item_ext<M>(I, t, smem); break;
         case kSAssoc: item_assoc<M>(I, t, smem); break;
@@ -1198,6 +1240,10 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, int32_t stop_stag
         } else if (U <= I.tail_max && F <= I.tail_front) {
             stage = kSPeelTail;
             items = 1;
+        } else if (I.bit_peel) {
+            stage = kSBuildF;  // then kSPhaseA over the tables
+            n = U;
+            items = cdiv(cdiv(F, kBlk), kEThreads / kWave);
         } else {
             const int32_t nJT = (int32_t)cdiv(U, kJT);
             int32_t IC = 4096 / MP;
@@ -1256,6 +1302,15 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, int32_t stop_stag
             case kSSplit1:
                 after_split(ld(&at<int32_t>(w, L.fsize)[arg]), ld(&at<int32_t>(w, L.usize)[arg]));
                 break;
+            case kSBuildF: {
+                constexpr int CB = blocks_per_chunk<M>();
+                const int32_t F = ld(&at<int32_t>(w, L.fsize)[arg]);
+                stage = kSPhaseA;
+                p0 = (int32_t)cdiv(cdiv(F, kBlk), CB);                  // chunks
+                p1 = (int32_t)cdiv(cdiv(n, kTileJ), kLevelTiles);       // tile groups
+                items = (int64_t)p0 * p1;
+                break;
+            }
             case kSPhaseA:
                 begin_level(arg + 1, n);
                 break;
