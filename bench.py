@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched measurement (512 selections in one graph launch)")
     ap.add_argument("--batch", type=int, default=512, help="instances in the batched plan")
+    ap.add_argument("--batch-only-m", type=int, default=0,
+                    help="diagnostics: keep only the batch's instances with this M")
     ap.add_argument("--engine-stats", action="store_true",
                     help="add the batched engine's per-stage block times (separate plan)")
     ap.add_argument("--plan-compare", action="store_true",
@@ -154,6 +156,8 @@ def batched(args):
     import paper_2503_20286_amd as nsga3
     import workloads
     ws = workloads.make_batch(args.batch)
+    if args.batch_only_m:
+        ws = [w for w in ws if w.M == args.batch_only_m]
     probs = [(torch.from_numpy(w.objs).cuda(), torch.from_numpy(w.refs).cuda(), w.K) for w in ws]
     ctx = nsga3.Context(0, autotune=True)
     ctx.reserve(max(w.N for w in ws), 5, 210)
@@ -235,18 +239,18 @@ def batched(args):
         extra["graph_of_single_calls_ms"] = start.elapsed_time(stop) / steps
         p3.close()
     return {
-        "value": args.batch / (ms_graph / 1e3),
+        "value": len(ws) / (ms_graph / 1e3),
         "unit": "selections/s",
         "ms_per_launch": ms_graph,
         "points_per_s": n_pts / (ms_graph / 1e3),
-        "instances": args.batch,
+        "instances": len(ws),
         "total_points": n_pts,
         "graph_branches": info["branches"],
         "graph_nodes": info["nodes"],
         "plan_create_s_with_autotune": t_create,
         "tuned_shapes": tuned,
         "single_calls_ms": ms_single,
-        "single_calls_sel_per_s": args.batch / (ms_single / 1e3),
+        "single_calls_sel_per_s": len(ws) / (ms_single / 1e3),
         "speedup_vs_single_calls": ms_single / ms_graph,
         "identical_to_single_calls": bool(same),
         "steps": steps,

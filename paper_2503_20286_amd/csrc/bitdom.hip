@@ -107,6 +107,8 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_all(const uint32_t *__restr
 // unranked list U_k.  Sizes come from the device; work items are handed out
 // by block index first, then by a counter.
 // ---------------------------------------------------------------------------
+constexpr int kFwdLevelTiles = 1;  // remaining-list tiles per item (2 and 4 measured slower)
+
 template <int M>
 __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
     const uint32_t *__restrict__ tabs, const uint32_t *__restrict__ uk,
@@ -123,14 +125,15 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
     if (nf == 0 || nu == 0) return;
     const int32_t nblk = (nf + kBlk - 1) / kBlk;
     const int32_t nIC = (nblk + CB - 1) / CB;
-    const int32_t nJT = (nu + kTileJ - 1) / kTileJ;
-    const int64_t nitems = (int64_t)nIC * nJT;
+    constexpr int T = kFwdLevelTiles;
+    const int32_t nJG = ((nu + kTileJ - 1) / kTileJ + T - 1) / T;
+    const int64_t nitems = (int64_t)nIC * nJG;
     int64_t item = blockIdx.x;
     while (item < nitems) {
-        const int32_t ic = (int32_t)(item / nJT);
-        const int32_t jt = (int32_t)(item % nJT);
+        const int32_t ic = (int32_t)(item / nJG);
+        const int32_t jg = (int32_t)(item % nJG);
         const int32_t b0 = ic * CB;
-        fwd_level_item<M, 1>(tabs, b0, min(CB, nblk - b0), uk, urun, nu, ucnt, jt, lt);
+        fwd_level_item<M, T>(tabs, b0, min(CB, nblk - b0), uk, urun, nu, ucnt, jg * T, lt);
         if (threadIdx.x == 0) s_item = (int32_t)(gridDim.x + atomicAdd(&work[level], 1u));
         __syncthreads();  // every wave is done with lt
         item = s_item;

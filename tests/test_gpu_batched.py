@@ -26,12 +26,16 @@ def _gpu():
     oracle.lib()
 
 
-@pytest.fixture(params=["engine", "graph"])
+@pytest.fixture(params=["engine", "engine_phased", "graph"])
 def plan_mode(request, monkeypatch):
+    """engine: per-class branches that overlap; engine_phased: every class's
+    counts between the two engine phases; graph: a graph of single calls."""
+    monkeypatch.delenv("NSGA3_PLAN_MODE", raising=False)
+    monkeypatch.delenv("NSGA3_PLAN_OVERLAP", raising=False)
     if request.param == "graph":
         monkeypatch.setenv("NSGA3_PLAN_MODE", "graph")
-    else:
-        monkeypatch.delenv("NSGA3_PLAN_MODE", raising=False)
+    elif request.param == "engine_phased":
+        monkeypatch.setenv("NSGA3_PLAN_OVERLAP", "0")
     return request.param
 
 
