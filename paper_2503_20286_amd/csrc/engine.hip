@@ -456,7 +456,15 @@ __device__ void item_splitw(const EInst &I, int32_t k, int32_t n, int32_t t, uin
                    smem, &nf, &nu);
 }
 
-// Whole split of a short list in one item; writes the level sizes.
+// Whether level k's front x remaining decrements run over front tables (the
+// choice the split's epilogue makes: not when the peeling ends or the one-item
+// tail takes over).
+__device__ __forceinline__ bool level_uses_tables(const EInst &I, int32_t F, int32_t U) {
+    return I.bit_peel && F > 0 && U > 0 && !(U <= I.tail_max && F <= I.tail_front);
+}
+
+// Whole split of a short list in one item; writes the level sizes, and the
+// front's block tables when the decrements will use them (one stage less).
 template <int M>
 __device__ void item_split1(const EInst &I, int32_t k, int32_t n, uint32_t *smem) {
     const ELayout &L = I.L;
@@ -474,6 +482,15 @@ __device__ void item_split1(const EInst &I, int32_t k, int32_t n, uint32_t *smem
     if (threadIdx.x == 0) {
         at<int32_t>(w, L.fsize)[k] = (int32_t)of;
         at<int32_t>(w, L.usize)[k] = (int32_t)ou;
+    }
+    if (level_uses_tables(I, (int32_t)of, (int32_t)ou)) {
+        __syncthreads();  // every wave's front records are written; the scan scratch is free
+        const uint32_t *fk = at<uint32_t>(w, (k & 1) ? L.fk1 : L.fk0);
+        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+        const int32_t nblk = (int32_t)cdiv(of, kBlk);
+        for (int32_t b = wv; b < nblk; b += kEThreads / kWave)
+            build_block<M, true>(fk, (int32_t)of, at<uint32_t>(w, L.tabs), b,
+                                 reinterpret_cast<int32_t *>(smem) + wv * kBlk);
     }
 }
 
@@ -847,38 +864,51 @@ __device__ void item_assoc(const EInst &I, int32_t t, uint32_t *smem) {
 #pragma unroll
         for (int k = 0; k < M; ++k) { fp[k] = 0.0; y[k] = 0.0f; }
     }
-    float smax = -FLT_MAX;
-    for (int32_t c0 = 0; c0 < H; c0 += HC) {
-        const int32_t hc = min(HC, H - c0);
-        __syncthreads();
-        for (int32_t q = threadIdx.x; q < hc * M; q += kEThreads) lr[q] = r32[(size_t)c0 * M + q];
-        __syncthreads();
-        for (int32_t j = 0; j < hc; ++j) {
-            float s = 0.0f;
-#pragma unroll
-            for (int k = 0; k < M; ++k) s = __fmaf_rn(y[k], lr[j * M + k], s);
-            smax = s > smax ? s : smax;
-        }
-    }
-    const float thr = smax - fp32_band<M>(l1);
     double d1 = DBL_MAX, d2 = DBL_MAX;
     int32_t best = 0;
-    for (int32_t c0 = 0; c0 < H; c0 += HC) {
-        const int32_t hc = min(HC, H - c0);
-        if (c0 > 0 || hc < H) {  // the single-chunk case still holds the chunk
+    const int32_t hm = H * M, hm2 = (hm + 1) & ~1;
+    if (hm2 + 2 * hm <= 8192) {
+        // both unit-reference forms in LDS (the float64 re-scoring then reads
+        // no global memory); the same screening as the single path
+        double *lr64 = reinterpret_cast<double *>(smem + hm2);
+        for (int32_t q = threadIdx.x; q < hm; q += kEThreads) {
+            lr[q] = r32[q];
+            lr64[q] = r64[q];
+        }
+        __syncthreads();
+        if (active) associate_point<M>(fp, y, l1, lr, lr64, H, best, d1, d2);
+    } else {
+        float smax = -FLT_MAX;
+        for (int32_t c0 = 0; c0 < H; c0 += HC) {
+            const int32_t hc = min(HC, H - c0);
             __syncthreads();
             for (int32_t q = threadIdx.x; q < hc * M; q += kEThreads) lr[q] = r32[(size_t)c0 * M + q];
             __syncthreads();
-        }
-        if (active) {
             for (int32_t j = 0; j < hc; ++j) {
                 float s = 0.0f;
 #pragma unroll
                 for (int k = 0; k < M; ++k) s = __fmaf_rn(y[k], lr[j * M + k], s);
-                if (s < thr) continue;
-                const double d = line_distance<M>(fp, r64 + (size_t)(c0 + j) * M);
-                if (d < d1) { d2 = d1; d1 = d; best = c0 + j; }
-                else if (d < d2) { d2 = d; }
+                smax = s > smax ? s : smax;
+            }
+        }
+        const float thr = smax - fp32_band<M>(l1);
+        for (int32_t c0 = 0; c0 < H; c0 += HC) {
+            const int32_t hc = min(HC, H - c0);
+            if (c0 > 0 || hc < H) {  // the single-chunk case still holds the chunk
+                __syncthreads();
+                for (int32_t q = threadIdx.x; q < hc * M; q += kEThreads) lr[q] = r32[(size_t)c0 * M + q];
+                __syncthreads();
+            }
+            if (active) {
+                for (int32_t j = 0; j < hc; ++j) {
+                    float s = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < M; ++k) s = __fmaf_rn(y[k], lr[j * M + k], s);
+                    if (s < thr) continue;
+                    const double d = line_distance<M>(fp, r64 + (size_t)(c0 + j) * M);
+                    if (d < d1) { d2 = d1; d1 = d; best = c0 + j; }
+                    else if (d < d2) { d2 = d; }
+                }
             }
         }
     }
@@ -1214,8 +1244,18 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, int32_t stop_stag
         if (n <= kESplitOne) { stage = kSSplit1; items = 1; }
         else { stage = kSSplitC; items = cdiv(n, kESplit); }
     };
-    // after the split of level arg: F fronts, U remaining (block-uniform)
-    auto after_split = [&](int32_t F, int32_t U) {
+    // bitset decrements of level arg over the front's tables
+    auto to_phase_a = [&](int32_t F, int32_t U) {
+        constexpr int CB = blocks_per_chunk<M>();
+        stage = kSPhaseA;
+        n = U;
+        p0 = (int32_t)cdiv(cdiv(F, kBlk), CB);             // chunks
+        p1 = (int32_t)cdiv(cdiv(U, kTileJ), kLevelTiles);  // tile groups
+        items = (int64_t)p0 * p1;
+    };
+    // after the split of level arg: F fronts, U remaining (block-uniform);
+    // tables_ready: the split item built the front's tables already
+    auto after_split = [&](int32_t F, int32_t U, bool tables_ready) {
         if (threadIdx.x == 0) {
             // a3: the first level whose cumulative size reaches K
             if (ld(&sc->last_front) < 0 && F > 0) {
@@ -1241,9 +1281,13 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, int32_t stop_stag
             stage = kSPeelTail;
             items = 1;
         } else if (I.bit_peel) {
-            stage = kSBuildF;  // then kSPhaseA over the tables
-            n = U;
-            items = cdiv(cdiv(F, kBlk), kEThreads / kWave);
+            if (tables_ready) {
+                to_phase_a(F, U);
+            } else {
+                stage = kSBuildF;  // then kSPhaseA over the tables
+                n = U;
+                items = cdiv(cdiv(F, kBlk), kEThreads / kWave);
+            }
         } else {
             const int32_t nJT = (int32_t)cdiv(U, kJT);
             int32_t IC = 4096 / MP;
@@ -1300,17 +1344,12 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, int32_t stop_stag
             }
             case kSSplitW:
             case kSSplit1:
-                after_split(ld(&at<int32_t>(w, L.fsize)[arg]), ld(&at<int32_t>(w, L.usize)[arg]));
+                after_split(ld(&at<int32_t>(w, L.fsize)[arg]), ld(&at<int32_t>(w, L.usize)[arg]),
+                            stage == kSSplit1);
                 break;
-            case kSBuildF: {
-                constexpr int CB = blocks_per_chunk<M>();
-                const int32_t F = ld(&at<int32_t>(w, L.fsize)[arg]);
-                stage = kSPhaseA;
-                p0 = (int32_t)cdiv(cdiv(F, kBlk), CB);                  // chunks
-                p1 = (int32_t)cdiv(cdiv(n, kTileJ), kLevelTiles);       // tile groups
-                items = (int64_t)p0 * p1;
+            case kSBuildF:
+                to_phase_a(ld(&at<int32_t>(w, L.fsize)[arg]), n);
                 break;
-            }
             case kSPhaseA:
                 begin_level(arg + 1, n);
                 break;
