@@ -540,8 +540,9 @@ static int n_range(int64_t N) { return N < 2048 ? 0 : N < 8192 ? 1 : N < 32768 ?
 
 static const EngineShape kShapeDefault = {8, nsga3::kETailDefault, nsga3::kETailFrontDefault};
 static const EngineShape kShapeCandidates[] = {
-    {8, 0, 0},        {8, 8192, 256},    {8, 8192, 1024},   {8, 32768, 256},
-    {8, 32768, 1024}, {32, 8192, 1024},  {32, 0, 0},
+    {8, 0, 0},        {8, 512, 128},     {8, 2048, 256},    {8, 8192, 256},
+    {8, 8192, 1024},  {8, 32768, 256},   {8, 32768, 1024},  {32, 8192, 1024},
+    {32, 0, 0},
 };
 
 // Times the whole engine pipeline on one group of instances (all of one M),

@@ -15,17 +15,22 @@
 
 namespace nsga3 {
 
+// Block tables of a list of n records (n_static, or *n_dev when n_static < 0):
+// each wave of a work-group builds one block.
+constexpr int kBuildWaves = 4;
+
 template <int M>
-__global__ __launch_bounds__(64) void k_build_blocks(const uint32_t *__restrict__ rec,
-                                                     int32_t n_static,
-                                                     const int32_t *__restrict__ n_dev,
-                                                     uint32_t *__restrict__ tabs,
-                                                     const DevScalars *__restrict__ sc) {
-    __shared__ int32_t inv[kBlk];
+__global__ __launch_bounds__(kBuildWaves * kWave) void k_build_blocks(
+    const uint32_t *__restrict__ rec, int32_t n_static, const int32_t *__restrict__ n_dev,
+    uint32_t *__restrict__ tabs, const DevScalars *__restrict__ sc) {
+    __shared__ int32_t inv[kBuildWaves][kBlk];
     if (sc->err) return;
     const int32_t n = n_static >= 0 ? n_static : *n_dev;
-    build_block<M>(rec, n, tabs, (int32_t)blockIdx.x, inv);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    build_block<M, true>(rec, n, tabs, (int32_t)blockIdx.x * kBuildWaves + w, inv[w]);
 }
+
+inline unsigned build_grid(int64_t nblk) { return (unsigned)((nblk + kBuildWaves - 1) / kBuildWaves); }
 
 // ---------------------------------------------------------------------------
 // In-degrees over all points.  A work-group owns kTilesPerItem point tiles
@@ -363,7 +368,7 @@ static hipError_t launch_counts(const SortViews &v, hipStream_t s) {
     const int32_t N = (int32_t)v.N;
     const int32_t nblk = (N + kBlk - 1) / kBlk;
     constexpr int CB = blocks_per_chunk<M>();
-    hipLaunchKernelGGL(k_build_blocks<M>, dim3((unsigned)nblk), dim3(64), 0, s, v.recs, N,
+    hipLaunchKernelGGL(k_build_blocks<M>, dim3(build_grid(nblk)), dim3(kBuildWaves * kWave), 0, s, v.recs, N,
                        (const int32_t *)nullptr, v.tabs_all, v.sc);
     const unsigned nIC = (unsigned)((nblk + CB - 1) / CB);
     const unsigned nJT = (unsigned)((N + kTileJ - 1) / kTileJ);
@@ -393,7 +398,7 @@ static void launch_level(const SortViews &v, const uint32_t *fk, const uint32_t 
                          const int32_t *urun, int32_t *ucnt, int level, unsigned grid, hipStream_t s) {
     const int32_t N = (int32_t)v.N;
     const int32_t nblk_max = (N + kBlk - 1) / kBlk;
-    hipLaunchKernelGGL(k_build_blocks<M>, dim3((unsigned)nblk_max), dim3(64), 0, s, fk, -1,
+    hipLaunchKernelGGL(k_build_blocks<M>, dim3(build_grid(nblk_max)), dim3(kBuildWaves * kWave), 0, s, fk, -1,
                        v.fsize + level, v.tabs_lvl, v.sc);
     hipLaunchKernelGGL(k_fwd_level<M>, dim3(grid), dim3(kFwdThreads), 0, s, v.tabs_lvl, uk, urun,
                        ucnt, level, v.fsize, v.usize, v.work, v.sc);
