@@ -152,9 +152,12 @@ __device__ __forceinline__ void build_block(const uint32_t *__restrict__ rec, in
     }
     for (int k = 0; k < M; ++k) {
         const uint32_t key = valid ? rec[(size_t)e * MP + k] : 0xffffffffu;
+        // rank among the block's keys (ties by lane); uniform lane reads
+        // (v_readlane) instead of 64 dependent LDS permutes
         uint32_t rank = 0;
+#pragma unroll
         for (int m = 0; m < kBlk; ++m) {
-            const uint32_t o = __shfl(key, m, 64);
+            const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)key, m);
             rank += (o < key || (o == key && m < l)) ? 1u : 0u;
         }
         T[blk_key_off(k) + rank] = key;

@@ -129,16 +129,20 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
     const int32_t nu = usize[level];
     if (nf == 0 || nu == 0) return;
     const int32_t nblk = (nf + kBlk - 1) / kBlk;
-    const int32_t nIC = (nblk + CB - 1) / CB;
     constexpr int T = kFwdLevelTiles;
     const int32_t nJG = ((nu + kTileJ - 1) / kTileJ + T - 1) / T;
+    // small levels: fewer tables per item while the items still fit in one
+    // round of the grid (shorter items, same number of rounds)
+    int32_t cb = CB;
+    while (cb > 1 && (int64_t)((nblk + cb / 2 - 1) / (cb / 2)) * nJG <= (int64_t)gridDim.x) cb >>= 1;
+    const int32_t nIC = (nblk + cb - 1) / cb;
     const int64_t nitems = (int64_t)nIC * nJG;
     int64_t item = blockIdx.x;
     while (item < nitems) {
         const int32_t ic = (int32_t)(item / nJG);
         const int32_t jg = (int32_t)(item % nJG);
-        const int32_t b0 = ic * CB;
-        fwd_level_item<M, T>(tabs, b0, min(CB, nblk - b0), uk, urun, nu, ucnt, jg * T, lt);
+        const int32_t b0 = ic * cb;
+        fwd_level_item<M, T>(tabs, b0, min(cb, nblk - b0), uk, urun, nu, ucnt, jg * T, lt);
         if (threadIdx.x == 0) s_item = (int32_t)(gridDim.x + atomicAdd(&work[level], 1u));
         __syncthreads();  // every wave is done with lt
         item = s_item;
