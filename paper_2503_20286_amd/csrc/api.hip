@@ -781,8 +781,9 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
         e = hipStreamCreateWithFlags(&bs, hipStreamNonBlocking);
         if (e == hipSuccess) pl->streams.push_back(bs);
     }
-    // events: fork, one per class for each of the two engine phases
-    for (int c = 0; c < 2 * nclass + 2 && e == hipSuccess; ++c) {
+    // events: one per class for each of the two engine phases, fork, join,
+    // one per class for its counts
+    for (int c = 0; c < 3 * nclass + 2 && e == hipSuccess; ++c) {
         hipEvent_t ev;
         e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e == hipSuccess) pl->events.push_back(ev);
@@ -814,8 +815,20 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
     };
     // Each class runs its three phases on its own branch, so one class's counts
     // overlap other classes' engines (6 % shorter launches on the mixed batch
-    // than counts with no engine running, which NSGA3_PLAN_OVERLAP=0 selects)
+    // than counts with no engine running, which NSGA3_PLAN_OVERLAP=0 selects).
+    // The classes' counts run one class at a time, in an order that starts the
+    // longest peeling first: ascending M, two-objective classes (one ordered
+    // ranking pass) last; NSGA3_PLAN_COUNT_ORDER=0 lets them run together.
     const bool overlap = !(getenv("NSGA3_PLAN_OVERLAP") && atoi(getenv("NSGA3_PLAN_OVERLAP")) == 0);
+    const bool ordered =
+        !(getenv("NSGA3_PLAN_COUNT_ORDER") && atoi(getenv("NSGA3_PLAN_COUNT_ORDER")) == 0);
+    std::vector<int> corder(nclass);
+    for (int c = 0; c < nclass; ++c) corder[c] = c;
+    std::stable_sort(corder.begin(), corder.end(), [&](int x, int y) {
+        const int mx = inst[cls[x].first].M, my = inst[cls[y].first].M;
+        return std::make_pair(mx == 2, mx) < std::make_pair(my == 2, my);
+    });
+    hipEvent_t *cev = ev + 2 * nclass + 2;  // counts of class c done
     // phase 1 (branch per class): keys, presort, records; parked before the counts
     e = hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) e = engine_init(pl->d_inst, pl->d_state, pl->d_glob, B, 2 * nclass, pl->cap);
@@ -827,8 +840,16 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
         if (e == hipSuccess)
             e = engine_launch(M, pl->d_inst, pl->d_state, cls[c].first, cls[c].second, pl->d_glob + c,
                               pl->d_stats, kSDom, grid[c], bs);
+    }
+    // (in count order, so that each wait names an event already recorded)
+    for (int q = 0; q < nclass && e == hipSuccess; ++q) {
+        const int c = corder[q];
+        const int M = inst[cls[c].first].M;
+        hipStream_t bs = pl->streams[c];
         if (overlap) {
+            if (ordered && q > 0) e = hipStreamWaitEvent(bs, cev[corder[q - 1]], 0);
             if (e == hipSuccess) e = counts(c, bs);
+            if (ordered && e == hipSuccess) e = hipEventRecord(cev[c], bs);
             if (e == hipSuccess)
                 e = engine_resume(pl->d_inst, pl->d_state, cls[c].first, cls[c].second,
                                   pl->d_glob + nclass + c, bs);
