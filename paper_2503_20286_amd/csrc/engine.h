@@ -47,7 +47,10 @@ enum EStage : int32_t {
     kSDone,
 };
 
-constexpr int kESplitOne = 4 * kESplit;  // lists up to this length split in one item
+// Lists up to this length split in one item (which also builds the front's
+// tables): limits of 4096, 8192, 16384 and 32768 entries took 14.4, 13.9,
+// 13.6 and 13.5 ms per launch on the mixed batch.
+constexpr int kESplitOne = 16 * kESplit;
 constexpr int kETailDefault = 8192;      // default EInst::tail_max
 constexpr int kETailFrontDefault = 1024; // default EInst::tail_front
 

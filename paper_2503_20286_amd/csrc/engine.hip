@@ -728,14 +728,17 @@ __device__ void item_build_f(const EInst &I, int32_t k, int32_t t, uint32_t *sme
 
 // a2, block-bitset form: one (chunk of front blocks, group of remaining
 // tiles) item of level k; p1 = tile groups.
-constexpr int kLevelTiles = 2;  // remaining-list tiles per item
+// Remaining-list tiles per item (whole table chunks per item): 1, 2, 4 and 8
+// tiles took 18.1, 14.4, 14.1 and 15.2 ms per launch on the mixed batch, and
+// splitting small levels into smaller chunks was slower still.
+constexpr int kLevelTiles = 4;
 static_assert(kEThreads == kFwdThreads, "engine work-groups run the bitset bodies");
 
 template <int M>
-__device__ void item_phase_a_bits(const EInst &I, int32_t k, int32_t ngroups, int32_t t,
+__device__ void item_phase_a_bits(const EInst &I, int32_t k, int32_t cb, int32_t ngroups, int32_t t,
                                   uint32_t *smem) {
-    constexpr int CB = blocks_per_chunk<M>();
-    static_assert(CB * blk_stride(M) <= kESmem, "a chunk of tables fits the worker's LDS");
+    static_assert(blocks_per_chunk<M>() * blk_stride(M) <= kESmem,
+                  "a chunk of tables fits the worker's LDS");
     const ELayout &L = I.L;
     char *w = I.ws;
     const int32_t nf = ld(&at<int32_t>(w, L.fsize)[k]);
@@ -743,8 +746,8 @@ __device__ void item_phase_a_bits(const EInst &I, int32_t k, int32_t ngroups, in
     const bool odd = (k & 1) != 0;
     const int32_t nblk = (int32_t)cdiv(nf, kBlk);
     const int32_t ic = t / ngroups, jg = t % ngroups;
-    const int32_t b0 = ic * CB;
-    fwd_level_item<M, kLevelTiles>(at<const uint32_t>(w, L.tabs), b0, min(CB, nblk - b0),
+    const int32_t b0 = ic * cb;
+    fwd_level_item<M, kLevelTiles>(at<const uint32_t>(w, L.tabs), b0, min(cb, nblk - b0),
                                    at<const uint32_t>(w, odd ? L.uk1 : L.uk0),
                                    at<const int32_t>(w, odd ? L.urun1 : L.urun0), nu,
                                    at<int32_t>(w, odd ? L.ucnt1 : L.ucnt0), jg * kLevelTiles, smem);
@@ -1037,7 +1040,7 @@ __device__ void run_item(const EInst &I, int32_t stage, int32_t arg, int32_t n,
         case kSPeelTail: item_peel_tail<M>(I, arg, smem); break;
         case kSRank2: item_rank2<M>(I, smem); break;
         case kSPhaseA:
-            if (I.bit_peel) item_phase_a_bits<M>(I, arg, p1, t, smem);
+            if (I.bit_peel) item_phase_a_bits<M>(I, arg, p0, p1, t, smem);
             else item_phase_a<M>(I, arg, p0, p1, t, smem);
             break;
         case kSBuildF: item_build_f<M>(I, arg, t, smem); break;
@@ -1249,9 +1252,9 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, int32_t stop_stag
         constexpr int CB = blocks_per_chunk<M>();
         stage = kSPhaseA;
         n = U;
-        p0 = (int32_t)cdiv(cdiv(F, kBlk), CB);             // chunks
+        p0 = CB;                                              // tables per item
         p1 = (int32_t)cdiv(cdiv(U, kTileJ), kLevelTiles);  // tile groups
-        items = (int64_t)p0 * p1;
+        items = cdiv(cdiv(F, kBlk), CB) * p1;
     };
     // after the split of level arg: F fronts, U remaining (block-uniform);
     // tables_ready: the split item built the front's tables already
