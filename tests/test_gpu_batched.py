@@ -132,6 +132,10 @@ def test_engine_edge_instances():
     cases.append((g2, workloads.das_dennis(2, 5).astype(np.float32), 1500))
     a7 = np.arange(7000, dtype=np.float32)
     cases.append((np.stack([a7, a7], axis=1), workloads.das_dennis(2, 5).astype(np.float32), 3500))
+    # lists longer than one split item takes (32768 entries): the two-stage
+    # level split (per-item counts, then ordered writes)
+    big = workloads.make_instance(9500, 40000, 3)
+    cases.append((big.objs, big.refs, big.K))
     # intercept fallbacks: equal objectives (singular), a constant objective (zero nadir)
     for col in (2, 0):
         f = rng.uniform(0, 1, (900, 3)).astype(np.float32)
