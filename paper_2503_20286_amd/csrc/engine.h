@@ -16,10 +16,11 @@ constexpr int kERsTile = 2048;     // keys per radix-sort item
 constexpr int kESplit = 2048;      // list entries per split item
 constexpr int kECmp = 2048;        // flags per compaction item
 constexpr int kESmem = 12288;      // LDS dwords per worker block
-// Presort key: the exact key sum (at most 36 bits for M <= 16, five 8-bit
-// passes); for M = 2 the lexicographic pair (key_1, key_2) (eight passes),
-// which is also a linear extension of dominance and lets the fronts be found
-// in one ordered pass (kSRank2).
+// Presort key: the exact key sum (at most 36 bits for M <= 16, at most five
+// 8-bit passes: the sort runs over key - min key, with as many passes as the
+// instance's key range needs); for M = 2 the lexicographic pair (key_1, key_2)
+// (eight passes), which is also a linear extension of dominance and lets the
+// fronts be found in one ordered pass (kSRank2).
 __host__ __device__ constexpr int radix_passes(int M) { return M == 2 ? 8 : 5; }
 
 __host__ __device__ constexpr int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -63,6 +64,8 @@ struct EScal {
     int32_t near_ties, level_V, ref_thr;
     uint32_t n_selected;
     int32_t rank2_overflow;  // the ordered pass found more fronts than it can hold
+    int32_t rs_passes;       // radix passes the presort takes (from the key range)
+    unsigned long long skey_min, skey_max;  // range of the presort keys (M >= 3)
     double z[16], a[16];
 };
 

@@ -105,6 +105,7 @@ __device__ void item_prep(const EInst &I, int32_t t, uint32_t *smem) {
     uint32_t lmin[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) lmin[k] = 0xffffffffu;
+    unsigned long long smn = ~0ull, smx = 0ull;  // range of the sum keys
     bool bad = false;
     uint64_t *skey = at<uint64_t>(w, L.skey0);
     uint32_t *sval = at<uint32_t>(w, L.sval0);
@@ -125,6 +126,9 @@ __device__ void item_prep(const EInst &I, int32_t t, uint32_t *smem) {
                 const uint32_t k0 = order_key(I.objs[(int64_t)p * M]);
                 const uint32_t k1 = order_key(I.objs[(int64_t)p * M + 1]);
                 s = ((uint64_t)k0 << 32) | (uint64_t)k1;
+            } else {
+                smn = s < smn ? s : smn;
+                smx = s > smx ? s : smx;
             }
             skey[p] = s;
             sval[p] = (uint32_t)p;
@@ -138,8 +142,27 @@ __device__ void item_prep(const EInst &I, int32_t t, uint32_t *smem) {
         if (lane_id() == 0) atomicMin(&smin[k], v);
     }
     if (ballot(bad) && lane_id() == 0) atomicOr(&sc->err, (uint32_t)kErrNonfiniteObj);
+    if (M != 2) {
+        smn = wave_min(smn);
+        smx = wave_max(smx);
+        if (lane_id() == 0 && smn <= smx) {
+            atomicMin(&sc->skey_min, smn);
+            atomicMax(&sc->skey_max, smx);
+        }
+    }
     __syncthreads();
     if ((int)threadIdx.x < M) atomicMin(&sc->min_key[threadIdx.x], smin[threadIdx.x]);
+}
+
+// What the radix passes subtract from the presort keys: the smallest sum key
+// (M >= 3), so that the passes cover only the instance's key range.
+__device__ __forceinline__ uint64_t key_base(const EInst &I, char *w) {
+    return I.M == 2 ? 0ull : ld(&at<EScal>(w, I.L.scal)->skey_min);
+}
+
+// Presort passes of an instance (set by the key-and-reference epilogue).
+__device__ __forceinline__ int sort_passes(const EInst &I) {
+    return ld(&at<EScal>(I.ws, I.L.scal)->rs_passes);
 }
 
 // Radix histogram of one tile (block-major: hist[tile][digit]).
@@ -147,6 +170,7 @@ __device__ void item_hist(const EInst &I, int pass, int32_t t, uint32_t *smem) {
     const ELayout &L = I.L;
     char *w = I.ws;
     const uint64_t *keys = at<uint64_t>(w, (pass & 1) ? L.skey1 : L.skey0);
+    const uint64_t kmin = key_base(I, w);
     uint32_t *h = smem;
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -154,7 +178,7 @@ __device__ void item_hist(const EInst &I, int pass, int32_t t, uint32_t *smem) {
 #pragma unroll
     for (int it = 0; it < kERsTile / kEThreads; ++it) {
         const int32_t p = t * kERsTile + it * kEThreads + (int32_t)threadIdx.x;
-        if (p < I.N) atomicAdd(&h[(uint32_t)(keys[p] >> shift) & 255u], 1u);
+        if (p < I.N) atomicAdd(&h[(uint32_t)((keys[p] - kmin) >> shift) & 255u], 1u);
     }
     __syncthreads();
     at<uint32_t>(w, L.hist)[(size_t)t * 256 + threadIdx.x] = h[threadIdx.x];
@@ -193,6 +217,7 @@ __device__ void item_scat(const EInst &I, int pass, int32_t t, uint32_t *smem) {
     }
     __syncthreads();
     const int shift = 8 * pass;
+    const uint64_t kmin = key_base(I, w);
     for (int it = 0; it < kERsTile / kEThreads; ++it) {
 #pragma unroll
         for (int q = 0; q < kEThreads / kWave; ++q) wc[q * 256 + tid] = 0;
@@ -200,7 +225,7 @@ __device__ void item_scat(const EInst &I, int pass, int32_t t, uint32_t *smem) {
         const int32_t p = t * kERsTile + it * kEThreads + (int32_t)tid;
         const bool valid = p < N;
         const uint64_t key = valid ? kin[p] : 0ull;
-        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint32_t d = (uint32_t)((key - kmin) >> shift) & 255u;
         uint64_t m = ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -235,7 +260,7 @@ __device__ void item_recs(const EInst &I, int32_t t) {
     constexpr int MP = rec_stride(M);
     char *w = I.ws;
     const int32_t N = I.N;
-    const bool odd = (radix_passes(M) & 1) != 0;  // where the last pass wrote
+    const bool odd = (sort_passes(I) & 1) != 0;  // where the last pass wrote
     const uint64_t *skey = at<uint64_t>(w, odd ? L.skey1 : L.skey0);
     const uint32_t *sval = at<uint32_t>(w, odd ? L.sval1 : L.sval0);
     uint32_t *recs = at<uint32_t>(w, L.recs);
@@ -757,7 +782,7 @@ __device__ void item_phase_a_bits(const EInst &I, int32_t k, int32_t cb, int32_t
 __device__ void item_orig(const EInst &I, int32_t t) {
     const ELayout &L = I.L;
     char *w = I.ws;
-    const uint32_t *sval = at<uint32_t>(w, (radix_passes(I.M) & 1) ? L.sval1 : L.sval0);
+    const uint32_t *sval = at<uint32_t>(w, (sort_passes(I) & 1) ? L.sval1 : L.sval0);
     const int32_t *rank_s = at<int32_t>(w, L.rank_s);
     const int32_t *din = at<int32_t>(w, L.din), *dout = at<int32_t>(w, L.dout);
     int32_t *rank = I.rank ? I.rank : at<int32_t>(w, L.rank);
@@ -1309,13 +1334,23 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, int32_t stop_stag
         }
         switch (stage) {
             case kSPrep:
+                if (threadIdx.x == 0) {
+                    int passes = radix_passes(M);
+                    if (M != 2) {  // 8-bit digits of (key - min key): the range's bits
+                        const unsigned long long lo = ld(&sc->skey_min), hi = ld(&sc->skey_max);
+                        const int bits = hi > lo ? 64 - __clzll((long long)(hi - lo)) : 0;
+                        passes = bits <= 8 ? 1 : (bits + 7) / 8;
+                    }
+                    sc->rs_passes = passes;
+                }
+                __syncthreads();
                 stage = kSHist; arg = 0; items = cdiv(N, kERsTile);
                 break;
             case kSHist:
                 stage = kSScat; items = cdiv(N, kERsTile);
                 break;
             case kSScat:
-                if (arg + 1 < radix_passes(M)) { stage = kSHist; ++arg; items = cdiv(N, kERsTile); }
+                if (arg + 1 < ld(&sc->rs_passes)) { stage = kSHist; ++arg; items = cdiv(N, kERsTile); }
                 else { stage = kSRecs; items = cdiv(N, kEChunk); }
                 break;
             case kSRecs: {
@@ -1601,6 +1636,9 @@ __global__ void k_engine_init(const EInst *__restrict__ inst, EState *st, EGloba
         sc->z[k] = 0.0;
         sc->a[k] = 1.0;
     }
+    sc->skey_min = ~0ull;
+    sc->skey_max = 0ull;
+    sc->rs_passes = radix_passes(I.M);
     sc->num_fronts = 0;
     sc->last_front = 0;
     sc->last_front_size = 0;
