@@ -105,12 +105,24 @@ __device__ __forceinline__ uint64_t low_bits(uint32_t c) {
 constexpr int kFwdThreads = 256;
 constexpr int kTJ = 2;                            // points per lane
 constexpr int kTileJ = kFwdThreads * kTJ;         // points per work item
-constexpr int kLdsTabDwords = 8704;               // 34 KiB of tables per work item
+// Tables staged per work-group: the all-pairs counts take 24 KiB chunks (more
+// resident work-groups per CU: 2.98 ms for both counts at N = 200k, M = 5,
+// against 3.24 ms with 34 KiB and 3.81 ms with 49 KiB); a peeling level's
+// items take 34 KiB (1.77 ms for the peel, against 1.82 ms with 24 KiB).
+#ifndef NSGA3_LDS_COUNT_DWORDS
+#define NSGA3_LDS_COUNT_DWORDS 6240
+#endif
+constexpr int kLdsCountDwords = NSGA3_LDS_COUNT_DWORDS;
+constexpr int kLdsLevelDwords = 8704;
 
-template <int M>
-__host__ __device__ constexpr int blocks_per_chunk() {
-    return kLdsTabDwords / blk_stride(M) < 1 ? 1 : kLdsTabDwords / blk_stride(M);
+template <int Dwords, int M>
+__host__ __device__ constexpr int chunk_blocks() {
+    return Dwords / blk_stride(M) < 1 ? 1 : Dwords / blk_stride(M);
 }
+template <int M>
+__host__ __device__ constexpr int count_chunk() { return chunk_blocks<kLdsCountDwords, M>(); }
+template <int M>
+__host__ __device__ constexpr int level_chunk() { return chunk_blocks<kLdsLevelDwords, M>(); }
 
 // ---------------------------------------------------------------------------
 // Tables: one wave per block of 64 consecutive list entries.

@@ -49,7 +49,7 @@ __device__ __forceinline__ void fwd_all_item(const uint32_t *__restrict__ tabs, 
                                              const int32_t *__restrict__ runstart, int32_t N,
                                              int32_t *__restrict__ dom_in, int32_t jg, int32_t cg,
                                              uint32_t *lt) {
-    constexpr int CB = blocks_per_chunk<M>();
+    constexpr int CB = count_chunk<M>();
     constexpr int T = kTilesPerItem;
     const int32_t nIC = (nblk + CB - 1) / CB;
     const int32_t jt0 = jg * T;
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_all(const uint32_t *__restr
                                                          const int32_t *__restrict__ runstart,
                                                          int32_t N, int32_t *__restrict__ dom_in,
                                                          const DevScalars *__restrict__ sc) {
-    __shared__ __attribute__((aligned(16))) uint32_t lt[blocks_per_chunk<M>() * blk_stride(M)];
+    __shared__ __attribute__((aligned(16))) uint32_t lt[count_chunk<M>() * blk_stride(M)];
     if (sc->err) return;
     fwd_all_item<M>(tabs, nblk, recs, runstart, N, dom_in, (int32_t)blockIdx.x, (int32_t)blockIdx.y, lt);
 }
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
     const int32_t *__restrict__ fsize, const int32_t *__restrict__ usize,
     uint32_t *__restrict__ work, const DevScalars *__restrict__ sc) {
     constexpr int TS = blk_stride(M);
-    constexpr int CB = blocks_per_chunk<M>();
+    constexpr int CB = level_chunk<M>();
     __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
     __shared__ int32_t s_item;
     if (sc->err) return;
@@ -203,7 +203,7 @@ __device__ __forceinline__ void bwd_all_item(const uint32_t *__restrict__ tabs, 
                                              const int32_t *__restrict__ runend, int32_t N,
                                              int32_t *__restrict__ dom_out, int32_t jg, int32_t cg,
                                              uint32_t *lt) {
-    constexpr int CB = blocks_per_chunk<M>();
+    constexpr int CB = count_chunk<M>();
     constexpr int MP = rec_stride(M);
     constexpr int T = kTilesPerItem;
     const int32_t nIC = (nblk + CB - 1) / CB;
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_bwd_all(const uint32_t *__restr
                                                          const int32_t *__restrict__ runend,
                                                          int32_t N, int32_t *__restrict__ dom_out,
                                                          const DevScalars *__restrict__ sc) {
-    __shared__ __attribute__((aligned(16))) uint32_t lt[blocks_per_chunk<M>() * blk_stride(M)];
+    __shared__ __attribute__((aligned(16))) uint32_t lt[count_chunk<M>() * blk_stride(M)];
     if (sc->err) return;
     bwd_all_item<M>(tabs, nblk, recs, runend, N, dom_out, (int32_t)blockIdx.x, (int32_t)blockIdx.y, lt);
 }
@@ -300,7 +300,7 @@ template <int M, bool kOut>
 __global__ __launch_bounds__(kFwdThreads) void k_eng_count(const EInst *__restrict__ inst,
                                                            const EState *__restrict__ st,
                                                            const int2 *__restrict__ map) {
-    constexpr int CB = blocks_per_chunk<M>();
+    constexpr int CB = count_chunk<M>();
     __shared__ __attribute__((aligned(16))) uint32_t lt[CB * blk_stride(M)];
     const int2 e = map[blockIdx.x];
     if (st[e.x].stage != kSDom) return;
@@ -350,7 +350,7 @@ hipError_t engine_bitdom_launch(int M, const EInst *inst, const EState *st, cons
 void engine_bitdom_items(int64_t N, int M, int64_t *n_build, int64_t *n_count) {
     int cb = 1;
     switch (M) {
-#define NSGA3_CB(m) case m: cb = blocks_per_chunk<m>(); break;
+#define NSGA3_CB(m) case m: cb = count_chunk<m>(); break;
         NSGA3_CB(2) NSGA3_CB(3) NSGA3_CB(4) NSGA3_CB(5) NSGA3_CB(6) NSGA3_CB(7) NSGA3_CB(8)
         NSGA3_CB(9) NSGA3_CB(10) NSGA3_CB(11) NSGA3_CB(12) NSGA3_CB(13) NSGA3_CB(14) NSGA3_CB(15)
         NSGA3_CB(16)
@@ -371,7 +371,7 @@ template <int M>
 static hipError_t launch_counts(const SortViews &v, hipStream_t s) {
     const int32_t N = (int32_t)v.N;
     const int32_t nblk = (N + kBlk - 1) / kBlk;
-    constexpr int CB = blocks_per_chunk<M>();
+    constexpr int CB = count_chunk<M>();
     hipLaunchKernelGGL(k_build_blocks<M>, dim3(build_grid(nblk)), dim3(kBuildWaves * kWave), 0, s, v.recs, N,
                        (const int32_t *)nullptr, v.tabs_all, v.sc);
     const unsigned nIC = (unsigned)((nblk + CB - 1) / CB);

@@ -762,7 +762,7 @@ static_assert(kEThreads == kFwdThreads, "engine work-groups run the bitset bodie
 template <int M>
 __device__ void item_phase_a_bits(const EInst &I, int32_t k, int32_t cb, int32_t ngroups, int32_t t,
                                   uint32_t *smem) {
-    static_assert(blocks_per_chunk<M>() * blk_stride(M) <= kESmem,
+    static_assert(level_chunk<M>() * blk_stride(M) <= kESmem,
                   "a chunk of tables fits the worker's LDS");
     const ELayout &L = I.L;
     char *w = I.ws;
@@ -1274,7 +1274,7 @@ __device__ void advance(const EInst &I, EState *S, EGlobal *g, int32_t stop_stag
     };
     // bitset decrements of level arg over the front's tables
     auto to_phase_a = [&](int32_t F, int32_t U) {
-        constexpr int CB = blocks_per_chunk<M>();
+        constexpr int CB = level_chunk<M>();
         stage = kSPhaseA;
         n = U;
         p0 = CB;                                              // tables per item
