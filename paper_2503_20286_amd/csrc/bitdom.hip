@@ -40,7 +40,10 @@ inline unsigned build_grid(int64_t nblk) { return (unsigned)((nblk + kBuildWaves
 // share their chunks in L2.  Chunks entirely after a tile's last run start
 // are skipped.
 // ---------------------------------------------------------------------------
-constexpr int kTilesPerItem = 4;
+// Tiles and chunks per count work-group: (tiles, chunks) = (2, 2) took
+// 2.87 ms for both counts at N = 200k, M = 5; (4, 2) 3.01, (6, 2) 3.27,
+// (1, 2) 2.92, (2, 1) 2.86, (2, 4) 2.93, (3, 2) 2.89, (4, 1) 2.97, (4, 3) 3.06.
+constexpr int kTilesPerItem = 2;
 constexpr int kChunksPerItem = 2;
 
 template <int M>
