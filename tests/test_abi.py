@@ -59,3 +59,14 @@ def test_library_missing_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.delenv("NSGA3_LIB")
     monkeypatch.setattr(_native, "_lib", None)
     importlib.reload(_native)
+
+
+def test_plan_stage_names_match_header():
+    """The binding names one stage per entry of the header's stage arrays."""
+    import re
+    from paper_2503_20286_amd import _native
+    hdr = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "nsga3.h")
+    with open(hdr) as fh:
+        m = re.search(r"#define NSGA3_PLAN_STAGES (\d+)", fh.read())
+    assert m and int(m.group(1)) == len(_native.PLAN_STAGES)
+    assert _native.PLAN_STAGES[-1] == "done"
