@@ -29,7 +29,9 @@
 namespace nsga3 {
 
 constexpr int kNormThreads = 256;
-constexpr int kRankGroup = 256;  // bucket members ranked per work-group
+constexpr int kRankGroup = 256;                   // threads of a bucket-rank work-group
+constexpr int kRankSplit = 4;                     // threads sharing one member's count
+constexpr int kRankMembers = kRankGroup / kRankSplit;  // members ranked per work-group
 constexpr int kNormBlocksMax = 256;
 
 // ---------------------------------------------------------------------------
@@ -448,7 +450,7 @@ __global__ __launch_bounds__(1024) void k_niche_plan(int H, const int32_t *__res
         }
         uint32_t tot, gtot;
         const uint32_t ex = block_exclusive_scan(v, lds, &tot);
-        const uint32_t gex = block_exclusive_scan((v + kRankGroup - 1) / kRankGroup, lds, &gtot);
+        const uint32_t gex = block_exclusive_scan((v + kRankMembers - 1) / kRankMembers, lds, &gtot);
         if (j < H) {
             bstart[j] = (int32_t)(run + ex);
             bcursor[j] = (int32_t)(run + ex);
@@ -550,8 +552,9 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(int64_t N, int H,
 
 // t_i = #members of the same reference with smaller (distance, index); pick
 // when (rho + t, reference) is below the threshold.  Work-group g ranks
-// kRankGroup members of one bucket (gstart maps groups to buckets) against the
-// whole bucket, staged through LDS.
+// kRankMembers members of one bucket (gstart maps groups to buckets) against
+// the whole bucket, staged through LDS; kRankSplit adjacent lanes share a
+// member, each counting every kRankSplit-th bucket entry.
 __global__ __launch_bounds__(kRankGroup) void k_bucket_rank(int H, const int32_t *__restrict__ rho,
                                                             const int32_t *__restrict__ bstart,
                                                             const int32_t *__restrict__ gstart,
@@ -572,7 +575,8 @@ __global__ __launch_bounds__(kRankGroup) void k_bucket_rank(int H, const int32_t
     }
     const int32_t j = lo;
     const int32_t b0 = bstart[j], b1 = bstart[j + 1];
-    const int32_t s = b0 + (g - gstart[j]) * kRankGroup + (int32_t)threadIdx.x;
+    const int32_t s = b0 + (g - gstart[j]) * kRankMembers + (int32_t)threadIdx.x / kRankSplit;
+    const int32_t sub = (int32_t)threadIdx.x % kRankSplit;
     const bool mine = s < b1;
     const double d = mine ? bd[s] : 0.0;
     const int32_t i = mine ? bi[s] : 0;
@@ -587,11 +591,13 @@ __global__ __launch_bounds__(kRankGroup) void k_bucket_rank(int H, const int32_t
         __syncthreads();
         if (mine) {
             const int32_t n = c1 - c0;
-#pragma unroll 8
-            for (int32_t m = 0; m < n; ++m) t += (sd[m] < d || (sd[m] == d && si[m] < i)) ? 1 : 0;
+#pragma unroll 4
+            for (int32_t m = sub; m < n; m += kRankSplit)
+                t += (sd[m] < d || (sd[m] == d && si[m] < i)) ? 1 : 0;
         }
     }
-    if (!mine) return;
+    for (int o = 1; o < kRankSplit; o <<= 1) t += __shfl_xor(t, o, 64);  // the member's lanes
+    if (!mine || sub != 0) return;
     const int64_t lev = (int64_t)rho[j] + t;
     const int64_t V = sc->level_V;
     if (lev < V || (lev == V && j < sc->ref_thr)) selflag[i] = 1;
@@ -667,8 +673,8 @@ hipError_t run_select_stage(const SelectViews &v, hipStream_t s) {
                        v.bcursor, v.gstart, v.sc);
     hipLaunchKernelGGL(k_bucket_scatter, dim3(nbN), dim3(256), 0, s, N, v.H, v.rank, v.niche, v.dist64,
                        v.bcursor, v.bd, v.bi, v.sc);
-    // at most ceil(|F_l| / kRankGroup) + H groups, |F_l| <= N
-    const unsigned nbG = (unsigned)((N + kRankGroup - 1) / kRankGroup + v.H);
+    // at most ceil(|F_l| / kRankMembers) + H groups, |F_l| <= N
+    const unsigned nbG = (unsigned)((N + kRankMembers - 1) / kRankMembers + v.H);
     hipLaunchKernelGGL(k_bucket_rank, dim3(nbG), dim3(kRankGroup), 0, s, v.H, v.rho, v.bstart,
                        v.gstart, v.bd, v.bi, v.selflag, v.sc);
     compact_flags(v.selflag, N, v.selected, v.K, v.temp, &v.sc->n_selected, s);
