@@ -472,25 +472,40 @@ __global__ __launch_bounds__(1024) void k_niche_plan(int H, const int32_t *__res
         s_vmax = m;
     }
     __syncthreads();
-    // binary search for V* in [0, vmax]: C is non-decreasing, C(0) = 0 <= R
-    int64_t lo = 0, hi = s_vmax;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        int64_t c = 0;
+    // binary search for V* in [0, vmax]: C is non-decreasing, C(0) = 0 <= R;
+    // the counts are read from LDS when they fit (one global read each, not
+    // one per search step)
+    constexpr int kLdsRefs = 4096;
+    __shared__ int32_t s_rho[kLdsRefs], s_bc[kLdsRefs];
+    const int32_t *rho_r = rho, *bc_r = bcount;
+    if (H <= kLdsRefs) {
         for (int j = threadIdx.x; j < H; j += blockDim.x) {
-            int64_t t = mid - rho[j];
-            t = t < 0 ? 0 : t;
-            c += t < bcount[j] ? t : bcount[j];
+            s_rho[j] = rho[j];
+            s_bc[j] = bcount[j];
         }
-        c = wave_sum(c);
         __syncthreads();
-        if (lane_id() == 0) red[threadIdx.x / kWave] = c;
-        __syncthreads();
-        int64_t tot = 0;
-        for (unsigned q = 0; q < blockDim.x / kWave; ++q) tot += red[q];
-        if (tot <= R) lo = mid; else hi = mid - 1;
+        rho_r = s_rho;
+        bc_r = s_bc;
     }
-    const int64_t V = lo;
+    // (one wave searches: no block barriers inside the loop)
+    __shared__ int64_t s_V;
+    if (threadIdx.x < kWave) {
+        int64_t lo = 0, hi = s_vmax;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            int64_t c = 0;
+            for (int j = threadIdx.x; j < H; j += kWave) {
+                int64_t t = mid - rho_r[j];
+                t = t < 0 ? 0 : t;
+                c += t < bc_r[j] ? t : bc_r[j];
+            }
+            c = wave_sum(c);
+            if (c <= R) lo = mid; else hi = mid - 1;
+        }
+        if (threadIdx.x == 0) s_V = lo;
+    }
+    __syncthreads();
+    const int64_t V = s_V;
     int64_t cV = 0;
     for (int j = threadIdx.x; j < H; j += blockDim.x) {
         int64_t t = V - rho[j];
