@@ -751,11 +751,11 @@ __device__ void item_build_f(const EInst &I, int32_t k, int32_t t, uint32_t *sme
                          reinterpret_cast<int32_t *>(smem) + wv * kBlk);
 }
 
-// a2, block-bitset form: one (chunk of front blocks, group of remaining
-// tiles) item of level k; p1 = tile groups.
-// Remaining-list tiles per item (whole table chunks per item): 1, 2, 4 and 8
-// tiles took 18.1, 14.4, 14.1 and 15.2 ms per launch on the mixed batch, and
-// splitting small levels into smaller chunks was slower still.
+// a2, block-bitset form: one (chunk of cb front tables, group of remaining
+// tiles) item of level k; p0 = cb, p1 = tile groups.  Remaining-list tiles per
+// item (whole table chunks per item): 1, 2, 4 and 8 tiles took 18.1, 14.4,
+// 14.1 and 15.2 ms per launch on the mixed batch, and splitting small levels
+// into smaller chunks was slower still.
 constexpr int kLevelTiles = 4;
 static_assert(kEThreads == kFwdThreads, "engine work-groups run the bitset bodies");
 
