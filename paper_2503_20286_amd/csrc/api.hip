@@ -413,12 +413,15 @@ nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt)
     c->ws_bytes = 0;
     c->profiling = false;
     c->ev_used = 0;
-    c->phase_a_bpc = 8;
     c->fixed_levels = 0;
     // NSGA3_PAIRWISE=1 selects the pairwise-compare dominance kernels instead
     // of the block-bitset ones (same results; kept for comparison)
     c->bitsets = true;
     if (const char *e = getenv("NSGA3_PAIRWISE")) c->bitsets = atoi(e) == 0;
+    // work-groups per CU of the per-level decrement kernels: the bitset level
+    // kernel's 34 KiB chunks let four stay resident (peel at N = 200k, M = 5:
+    // 1.74 ms with 4 per CU, 1.76 with 8, 1.78 with 16, 1.90 with 3)
+    c->phase_a_bpc = c->bitsets ? 4 : 8;
     // NSGA3_TAIL_BLOCK=1: finish peeling in one workgroup instead of the
     // cooperative grid (the form captured graphs use; same results)
     c->tail_block = false;
