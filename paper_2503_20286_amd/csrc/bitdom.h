@@ -140,9 +140,13 @@ __device__ __forceinline__ void block_sync() {
 
 // kWaveSync: the calling wave builds its block alone (work-groups of several
 // waves, each with its own inv[64]); otherwise the work-group is this one wave.
+// The calling wave writes the objectives k0, k0 + kstep, ... of the table
+// (and the header and positions when k0 == 0), so several waves can share one
+// table.
 template <int M, bool kWaveSync = false>
 __device__ __forceinline__ void build_block(const uint32_t *__restrict__ rec, int32_t n,
-                                            uint32_t *__restrict__ tabs, int32_t b, int32_t *inv) {
+                                            uint32_t *__restrict__ tabs, int32_t b, int32_t *inv,
+                                            int k0 = 0, int kstep = 1) {
     constexpr int MP = rec_stride(M);
     constexpr int TS = blk_stride(M);
     if ((int64_t)b * kBlk >= n) return;
@@ -151,18 +155,20 @@ __device__ __forceinline__ void build_block(const uint32_t *__restrict__ rec, in
     const bool valid = e < n;
     const int32_t nmem = min(kBlk, n - b * kBlk);
     uint32_t *T = tabs + (size_t)b * TS;
-    const int32_t pos = valid ? (int32_t)rec[(size_t)e * MP + M] : 0x7fffffff;
-    T[blk_pos_off() + l] = (uint32_t)pos;
-    // (no uniform-address loads: a persistent caller's records change between
-    // stages, and a scalar load could hit a stale scalar-cache line)
-    const int32_t last = __shfl(pos, nmem - 1, 64);
-    if (l == 0) {
-        T[0] = (uint32_t)pos;
-        T[1] = (uint32_t)last;
-        T[2] = (uint32_t)nmem;
-        T[3] = 0;
+    if (k0 == 0) {
+        const int32_t pos = valid ? (int32_t)rec[(size_t)e * MP + M] : 0x7fffffff;
+        T[blk_pos_off() + l] = (uint32_t)pos;
+        // (no uniform-address loads: a persistent caller's records change
+        // between stages, and a scalar load could hit a stale scalar-cache line)
+        const int32_t last = __shfl(pos, nmem - 1, 64);
+        if (l == 0) {
+            T[0] = (uint32_t)pos;
+            T[1] = (uint32_t)last;
+            T[2] = (uint32_t)nmem;
+            T[3] = 0;
+        }
     }
-    for (int k = 0; k < M; ++k) {
+    for (int k = k0; k < M; k += kstep) {
         const uint32_t key = valid ? rec[(size_t)e * MP + k] : 0xffffffffu;
         // rank among the block's keys (ties by lane); uniform lane reads
         // (v_readlane) instead of 64 dependent LDS permutes

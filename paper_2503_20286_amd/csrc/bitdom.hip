@@ -16,7 +16,9 @@
 namespace nsga3 {
 
 // Block tables of a list of n records (n_static, or *n_dev when n_static < 0):
-// each wave of a work-group builds one block.
+// one table per work-group, its objectives spread over the waves (a table's
+// latency is that of ceil(M / kBuildWaves) objectives, which matters for the
+// small fronts of late peeling levels).
 constexpr int kBuildWaves = 4;
 
 template <int M>
@@ -27,10 +29,10 @@ __global__ __launch_bounds__(kBuildWaves * kWave) void k_build_blocks(
     if (sc->err) return;
     const int32_t n = n_static >= 0 ? n_static : *n_dev;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    build_block<M, true>(rec, n, tabs, (int32_t)blockIdx.x * kBuildWaves + w, inv[w]);
+    build_block<M, true>(rec, n, tabs, (int32_t)blockIdx.x, inv[w], w, kBuildWaves);
 }
 
-inline unsigned build_grid(int64_t nblk) { return (unsigned)((nblk + kBuildWaves - 1) / kBuildWaves); }
+inline unsigned build_grid(int64_t nblk) { return (unsigned)nblk; }
 
 // ---------------------------------------------------------------------------
 // In-degrees over all points.  A work-group owns kTilesPerItem point tiles
