@@ -211,10 +211,10 @@ __device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__re
 
 // Forward: for each of the wave's kTJ x 64 points j (keys kj, run starts run),
 // add the number of members of the staged blocks that dominate j.
-template <int M>
+template <int M, int TJ = kTJ>
 __device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32_t run_lo,
-                                           int32_t run_hi, const uint32_t (&kj)[kTJ][M],
-                                           const int32_t (&run)[kTJ], int32_t (&cnt)[kTJ]) {
+                                           int32_t run_hi, const uint32_t (&kj)[TJ][M],
+                                           const int32_t (&run)[TJ], int32_t (&cnt)[TJ]) {
     constexpr int TS = blk_stride(M);
     for (int32_t b = 0; b < nb; ++b) {
         const uint32_t *T = lt + b * TS;
@@ -222,19 +222,19 @@ __device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32
         const int32_t bmax = (int32_t)T[1];
         if (bmin >= run_hi) break;  // later blocks start later still
         const bool full = bmax < run_lo;
-        // the kTJ x M key searches in lockstep
-        const uint32_t *S[kTJ * M];
-        uint32_t x[kTJ * M], c[kTJ * M];
+        // the TJ x M key searches in lockstep
+        const uint32_t *S[TJ * M];
+        uint32_t x[TJ * M], c[TJ * M];
 #pragma unroll
-        for (int t = 0; t < kTJ; ++t)
+        for (int t = 0; t < TJ; ++t)
 #pragma unroll
             for (int k = 0; k < M; ++k) {
                 S[t * M + k] = T + blk_key_off(k);
                 x[t * M + k] = kj[t][k];
             }
-        count_many64<kTJ * M, true>(S, x, c);
+        count_many64<TJ * M, true>(S, x, c);
 #pragma unroll
-        for (int t = 0; t < kTJ; ++t) {
+        for (int t = 0; t < TJ; ++t) {
             uint64_t m = ~0ull;
             if (!full) {
                 if (run[t] <= bmin) m = 0ull;
@@ -250,14 +250,14 @@ __device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32
 }
 
 // Loads the wave's points (records with MP stride, run starts) into registers.
-template <int M>
+template <int M, int TJ = kTJ>
 __device__ __forceinline__ void load_points(const uint32_t *__restrict__ jrec,
                                             const int32_t *__restrict__ jrun, int32_t nj,
-                                            int32_t jbase, int lane, uint32_t (&kj)[kTJ][M],
-                                            int32_t (&run)[kTJ]) {
+                                            int32_t jbase, int lane, uint32_t (&kj)[TJ][M],
+                                            int32_t (&run)[TJ]) {
     constexpr int MP = rec_stride(M);
 #pragma unroll
-    for (int t = 0; t < kTJ; ++t) {
+    for (int t = 0; t < TJ; ++t) {
         const int32_t q = jbase + t * kWave + lane;
         if (q < nj) {
 #pragma unroll
@@ -281,20 +281,20 @@ __device__ __forceinline__ T vld(const T *p) {
 }
 
 // One item of a peeling level (Eq. (9)): the front blocks [b0, b0 + nb) (one
-// chunk, staged in lt) against T consecutive tiles of the remaining list from
-// tile jt0; every remaining point's count drops by the chunk members that
+// chunk, staged in lt) against T consecutive tiles (kFwdThreads * TJ points
+// each, TJ per lane) of the remaining list from tile jt0; every remaining point's count drops by the chunk members that
 // dominate it.  The whole work-group (kFwdThreads) calls it with uniform
 // arguments; it returns early, before any barrier, when every chunk member
 // lies at or after the tiles' last run start.
-template <int M, int T>
+template <int M, int T, int TJ = kTJ>
 __device__ __forceinline__ void fwd_level_item(const uint32_t *__restrict__ tabs, int32_t b0,
                                                int32_t nb, const uint32_t *__restrict__ uk,
                                                const int32_t *__restrict__ urun, int32_t nu,
                                                int32_t *__restrict__ ucnt, int32_t jt0,
                                                uint32_t *lt) {
     constexpr int TS = blk_stride(M);
-    if (jt0 * kTileJ >= nu) return;
-    const int32_t tile_last = min((jt0 + T) * kTileJ, nu) - 1;
+    if (jt0 * (kFwdThreads * TJ) >= nu) return;
+    const int32_t tile_last = min((jt0 + T) * (kFwdThreads * TJ), nu) - 1;
     if ((int32_t)vld(&tabs[(size_t)b0 * TS]) >= vld(&urun[tile_last])) return;
     stage_tables<M>(lt, tabs, b0, nb);
     __syncthreads();
@@ -302,18 +302,18 @@ __device__ __forceinline__ void fwd_level_item(const uint32_t *__restrict__ tabs
     const int lane = (int)lane_id();
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-        const int32_t jbase = (jt0 + t) * kTileJ + w * kWave * kTJ;
+        const int32_t jbase = (jt0 + t) * (kFwdThreads * TJ) + w * kWave * TJ;
         if (jbase >= nu) break;
-        uint32_t kj[kTJ][M];
-        int32_t run[kTJ], cnt[kTJ];
-        load_points<M>(uk, urun, nu, jbase, lane, kj, run);
+        uint32_t kj[TJ][M];
+        int32_t run[TJ], cnt[TJ];
+        load_points<M, TJ>(uk, urun, nu, jbase, lane, kj, run);
 #pragma unroll
-        for (int u = 0; u < kTJ; ++u) cnt[u] = 0;
+        for (int u = 0; u < TJ; ++u) cnt[u] = 0;
         const int32_t run_lo = vld(&urun[jbase]);
-        const int32_t run_hi = vld(&urun[min(jbase + kWave * kTJ - 1, nu - 1)]);
-        fwd_blocks<M>(lt, nb, run_lo, run_hi, kj, run, cnt);
+        const int32_t run_hi = vld(&urun[min(jbase + kWave * TJ - 1, nu - 1)]);
+        fwd_blocks<M, TJ>(lt, nb, run_lo, run_hi, kj, run, cnt);
 #pragma unroll
-        for (int u = 0; u < kTJ; ++u) {
+        for (int u = 0; u < TJ; ++u) {
             const int32_t q = jbase + u * kWave + lane;
             if (q < nu && cnt[u]) atomicSub(&ucnt[q], cnt[u]);
         }

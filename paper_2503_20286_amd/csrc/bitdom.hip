@@ -118,6 +118,10 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_all(const uint32_t *__restr
 // by block index first, then by a counter.
 // ---------------------------------------------------------------------------
 constexpr int kFwdLevelTiles = 1;  // remaining-list tiles per item (2 and 4 measured slower)
+// Points per lane of the level kernel: 3 took the peel at N = 200k, M = 5 from
+// 1.64 to 1.57 ms (the all-pairs counts keep kTJ = 2, their best).
+constexpr int kLevelTJ = 3;
+constexpr int kLevelTileJ = kFwdThreads * kLevelTJ;
 
 template <int M>
 __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
@@ -135,7 +139,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
     if (nf == 0 || nu == 0) return;
     const int32_t nblk = (nf + kBlk - 1) / kBlk;
     constexpr int T = kFwdLevelTiles;
-    const int32_t nJG = ((nu + kTileJ - 1) / kTileJ + T - 1) / T;
+    const int32_t nJG = ((nu + kLevelTileJ - 1) / kLevelTileJ + T - 1) / T;
     // small levels: fewer tables per item while the items still fit in one
     // round of the grid (shorter items, same number of rounds)
     int32_t cb = CB;
@@ -147,7 +151,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
         const int32_t ic = (int32_t)(item / nJG);
         const int32_t jg = (int32_t)(item % nJG);
         const int32_t b0 = ic * cb;
-        fwd_level_item<M, T>(tabs, b0, min(cb, nblk - b0), uk, urun, nu, ucnt, jg * T, lt);
+        fwd_level_item<M, T, kLevelTJ>(tabs, b0, min(cb, nblk - b0), uk, urun, nu, ucnt, jg * T, lt);
         if (threadIdx.x == 0) s_item = (int32_t)(gridDim.x + atomicAdd(&work[level], 1u));
         __syncthreads();  // every wave is done with lt
         item = s_item;
