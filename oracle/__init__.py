@@ -43,11 +43,14 @@ def _declare(L):
     L.oracle_associate.argtypes = [P, i64, i32, P, ctypes.c_int32, P, P, P, i32, P, P, P]
     L.oracle_niche_count.argtypes = [P, P, i64, ctypes.c_int32, i32, P]
     L.oracle_niching.argtypes = [P, P, P, i64, ctypes.c_int32, i32, i64, P, P]
+    L.oracle_niching_oneshot.argtypes = [P, P, P, i64, ctypes.c_int32, i32, i64, P, P, P]
     L.oracle_select.argtypes = [P, i64, i32, P, i32, i64, P, P, P, P, P, P, P]
+    L.oracle_select_mode.argtypes = [P, i64, i32, P, i32, i64, i32, P, P, P, P, P, P, P]
     L.oracle_num_threads.argtypes = []
     for name in ("oracle_dominates", "oracle_dominance", "oracle_dominance_one", "oracle_ranks",
                  "oracle_last_front", "oracle_normalize", "oracle_associate",
-                 "oracle_niche_count", "oracle_niching", "oracle_select", "oracle_num_threads"):
+                 "oracle_niche_count", "oracle_niching", "oracle_niching_oneshot",
+                 "oracle_select", "oracle_select_mode", "oracle_num_threads"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -101,7 +104,7 @@ def dominates(objs, i, j) -> bool:
 
 
 def ranks(objs):
-    """(rank int32[N], number of fronts) by front peeling."""
+    """(rank int32[N], number of fronts): rank = longest dominance chain ending at the point."""
     f = _objs(objs)
     N, M = f.shape
     r = np.zeros(N, np.int32)
@@ -179,6 +182,23 @@ def niching(rank, niche, dist, l, H, R, rho):
     return chosen.astype(bool)
 
 
+def niching_oneshot(rank, niche, dist, l, H, R, rho):
+    """(bool[N] admitted last-front members, |E|) of the one-shot niche selection."""
+    r = np.ascontiguousarray(rank, dtype=np.int32)
+    n = np.ascontiguousarray(niche, dtype=np.int32)
+    d = np.ascontiguousarray(dist, dtype=np.float64)
+    rh = np.ascontiguousarray(rho, dtype=np.int32)
+    chosen = np.zeros(r.size, np.uint8)
+    ne = ctypes.c_int64()
+    _check(lib().oracle_niching_oneshot(_ptr(r), _ptr(n), _ptr(d), r.size, int(l), int(H), int(R),
+                                        _ptr(rh), _ptr(chosen), ctypes.byref(ne)),
+           "oracle_niching_oneshot")
+    return chosen.astype(bool), ne.value
+
+
+NICHING = {"exact": 0, "oneshot": 1}
+
+
 @dataclass
 class Selection:
     selected: np.ndarray
@@ -195,8 +215,9 @@ class Selection:
     near_ties: int
 
 
-def select(objs, refs, K, with_counts=True):
-    """Whole environmental selection on the CPU (float64)."""
+def select(objs, refs, K, with_counts=True, niching="exact"):
+    """Whole environmental selection on the CPU (float64).  niching: "exact"
+    (the loop of Alg. S.1) or "oneshot" (the one-shot form of Alg. S.4)."""
     f = _objs(objs)
     N, M = f.shape
     R = np.ascontiguousarray(refs, dtype=np.float32)
@@ -207,7 +228,8 @@ def select(objs, refs, K, with_counts=True):
     din = np.zeros(N, np.int32) if with_counts else None
     dout = np.zeros(N, np.int32) if with_counts else None
     info = np.zeros(6, np.int64)
-    _check(lib().oracle_select(_ptr(f), N, M, _ptr(R), R.shape[0], int(K), _ptr(sel), _ptr(rank),
-                               _ptr(niche), _ptr(dist), _ptr(din), _ptr(dout), _ptr(info)),
-           "oracle_select")
+    _check(lib().oracle_select_mode(_ptr(f), N, M, _ptr(R), R.shape[0], int(K), NICHING[niching],
+                                    _ptr(sel), _ptr(rank), _ptr(niche), _ptr(dist), _ptr(din),
+                                    _ptr(dout), _ptr(info)),
+           "oracle_select_mode")
     return Selection(sel, rank, niche, dist, din, dout, *[int(v) for v in info])

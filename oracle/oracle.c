@@ -11,19 +11,20 @@
  *
  * Stages (each function cites the passage it follows):
  *   oracle_dominance   Pareto dominance (Listing 1, Eq. (6)), in/out degree (Eq. (7))
- *   oracle_ranks       tensorized nondominated sort, front peeling (Eq. (8)-(9), Alg. S.3)
+ *   oracle_ranks       nondominated front of every point (Eq. (8)-(9), Alg. S.3)
  *   oracle_last_front  last admitted front l (Sec. IV-A.1, last step of Alg. S.3)
  *   oracle_normalize   ideal point, extreme points, intercepts (Alg. S.5)
  *   oracle_associate   perpendicular distance to reference lines (Eq. (10))
  *   oracle_niche_count niche counts over admitted fronts (Eq. (11))
  *   oracle_niching     niche-preserving pick from the last front (Alg. S.1)
+ *   oracle_niching_oneshot  the one-shot niche selection (Sec. IV-A.5, Alg. S.4, Alg. S.6)
  *   oracle_select      the whole environmental selection (Alg. S.1 / S.4 outputs, Eq. (13))
  *
  * Readings of points the paper leaves open are fixed here and listed in the
  * design notes:
  *   - c counts the dominators of each point (the in-degree); only that makes
  *     p = 1{c = 0} the non-dominated set and matches the decrement sum_i p_i D_ij.
- *   - ranks are 0-based; a peeled point is retired (c - p makes it -1).
+ *   - ranks are 0-based: front 0 holds the points nothing dominates.
  *   - l is the rank of the K-th smallest rank (0-based position K-1).
  *   - S = {r <= l}; the ideal point is taken over S.
  *   - extreme points use the achievement scalarising function with weight 1 on
@@ -121,51 +122,62 @@ int oracle_dominance_one(const float *objs, int64_t N, int M, int64_t j,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Tensorized nondominated sort, Eq. (8)-(9) and Alg. S.3.                    */
-/*   c <- in-degree;  r <- 0;  k <- 0;  p <- 1{c = 0}                         */
-/*   while any(p): r[p] <- k;  d_j <- sum_i p_i D_ij;  c <- c - d - p;        */
-/*                 k <- k + 1;  p <- 1{c = 0}                                  */
-/* D_ij is evaluated on demand instead of being stored.                        */
+/* Nondominated fronts, Eq. (8)-(9) and Alg. S.3.                            */
+/* The peeling of Eq. (8)-(9) puts a point in front k exactly when all of its */
+/* dominators lie in fronts below k and one of them in front k-1, so          */
+/*   rank[j] = 0                          if nothing dominates j,             */
+/*   rank[j] = 1 + max{rank[i] : i dom j}  otherwise                          */
+/* (the length of the longest dominance chain ending at j).  That recursion   */
+/* is evaluated here directly, visiting the points in an order in which every */
+/* dominator comes first: ascending float64 sum of the objectives, then       */
+/* lexicographic objectives, then index.  If i dominates j, each term of i's  */
+/* sum is <= j's and rounding is monotone, so sum_i <= sum_j; with equal sums */
+/* the first objective where the two differ is smaller for i.                 */
 /* ------------------------------------------------------------------------ */
+typedef struct { double sum; int64_t i; const float *row; int M; } order_key_t;
+
+static int cmp_order(const void *pa, const void *pb)
+{
+    const order_key_t *a = (const order_key_t *)pa, *b = (const order_key_t *)pb;
+    if (a->sum < b->sum) return -1;
+    if (a->sum > b->sum) return 1;
+    for (int k = 0; k < a->M; ++k) {
+        double x = (double)a->row[k], y = (double)b->row[k];
+        if (x < y) return -1;
+        if (x > y) return 1;
+    }
+    return (a->i < b->i) ? -1 : (a->i > b->i);
+}
+
 int oracle_ranks(const float *objs, int64_t N, int M, int32_t *rank, int32_t *num_fronts)
 {
     if (!objs || !rank || N < 1 || M < 1) return OR_EINVAL;
     if (!check_finite(objs, N * M)) return OR_ENONFINITE;
-    int64_t *c = (int64_t *)malloc(sizeof(int64_t) * N);
-    int64_t *front = (int64_t *)malloc(sizeof(int64_t) * N);
-    int64_t *d = (int64_t *)malloc(sizeof(int64_t) * N);
-    if (!c || !front || !d) { free(c); free(front); free(d); return OR_EINVAL; }
-
-    #pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t j = 0; j < N; ++j) {
-        int64_t cnt = 0;
-        for (int64_t i = 0; i < N; ++i)
-            if (i != j && dominates(objs, M, i, j)) ++cnt;
-        c[j] = cnt;
-        rank[j] = 0;
+    order_key_t *ord = (order_key_t *)malloc(sizeof(order_key_t) * (size_t)N);
+    if (!ord) return OR_EINVAL;
+    for (int64_t i = 0; i < N; ++i) {
+        double s = 0.0;
+        for (int k = 0; k < M; ++k) s = s + (double)objs[i * M + k];
+        ord[i].sum = s;
+        ord[i].i = i;
+        ord[i].row = objs + i * M;
+        ord[i].M = M;
     }
-
-    int32_t k = 0;
-    for (;;) {
-        int64_t nf = 0;
-        for (int64_t j = 0; j < N; ++j)
-            if (c[j] == 0) front[nf++] = j;          /* p = 1{c = 0} */
-        if (nf == 0) break;                          /* while any(p) */
-        for (int64_t t = 0; t < nf; ++t) rank[front[t]] = k;   /* r[p] <- k */
-        #pragma omp parallel for schedule(dynamic, 64)
-        for (int64_t j = 0; j < N; ++j) {            /* d_j = sum_i p_i D_ij */
-            int64_t s = 0;
-            if (c[j] > 0)
-                for (int64_t t = 0; t < nf; ++t)
-                    if (dominates(objs, M, front[t], j)) ++s;
-            d[j] = s;
+    qsort(ord, (size_t)N, sizeof(order_key_t), cmp_order);
+    int32_t L = 0;
+    for (int64_t t = 0; t < N; ++t) {
+        const int64_t j = ord[t].i;
+        int32_t best = -1;   /* highest rank among the dominators of j seen so far */
+        #pragma omp parallel for schedule(static) reduction(max : best) if (t > 4096)
+        for (int64_t u = 0; u < t; ++u) {
+            const int64_t i = ord[u].i;
+            if (dominates(objs, M, i, j) && rank[i] > best) best = rank[i];
         }
-        for (int64_t j = 0; j < N; ++j) c[j] -= d[j];           /* c <- c - d */
-        for (int64_t t = 0; t < nf; ++t) c[front[t]] -= 1;      /*      - p   */
-        ++k;
+        rank[j] = best + 1;
+        if (rank[j] + 1 > L) L = rank[j] + 1;
     }
-    if (num_fronts) *num_fronts = k;
-    free(c); free(front); free(d);
+    if (num_fronts) *num_fronts = L;
+    free(ord);
     return OR_OK;
 }
 
@@ -368,13 +380,13 @@ int oracle_niche_count(const int32_t *rank, const int32_t *niche, int64_t N, int
 }
 
 /* ------------------------------------------------------------------------ */
-/* Niche-preserving pick, Alg. S.1 (its inner while loop):                    */
-/*   while fewer than n chosen:                                              */
-/*     j <- least crowded active reference (lowest j on ties);               */
-/*     if no remaining last-front member is associated with j: drop j;       */
-/*     else take its closest remaining member (distance, then index) and     */
-/*          increase rho_j.                                                  */
-/* chosen[i] is set to 1 for the picked last-front members.                  */
+/* Niche-preserving pick from the last front, Alg. S.1.                       */
+/* The rule: R members of F_l are admitted one at a time.  Each admission     */
+/* goes to the reference with the smallest niche count rho_j among those that */
+/* still have unadmitted F_l members associated with them (lowest j on ties); */
+/* that reference admits its closest such member (smallest distance, then     */
+/* lowest index -- one of the outcomes the paper's random choice allows) and  */
+/* its niche count grows by one.  chosen[i] = 1 for the admitted members.     */
 /* ------------------------------------------------------------------------ */
 typedef struct { double d; int64_t i; } dkey_t;
 
@@ -386,72 +398,125 @@ static int cmp_dkey(const void *pa, const void *pb)
     return (a->i < b->i) ? -1 : (a->i > b->i);
 }
 
+/* Members of F_l grouped by reference, each group in (distance, index) order:
+ * group j occupies cand[first[j] .. first[j+1]).  Returns |F_l|, or -1 when a
+ * member's reference is out of range or memory runs out. */
+static int64_t group_last_front(const int32_t *rank, const int32_t *niche, const double *dist,
+                                int64_t N, int32_t l, int H, dkey_t **cand_out, int64_t **first_out)
+{
+    int64_t *first = (int64_t *)calloc((size_t)H + 1, sizeof(int64_t));
+    int64_t *fill = (int64_t *)calloc((size_t)H, sizeof(int64_t));
+    int64_t nl = 0;
+    if (!first || !fill) { free(first); free(fill); return -1; }
+    for (int64_t i = 0; i < N; ++i) {
+        if (rank[i] != l) continue;
+        if (niche[i] < 0 || niche[i] >= H) { free(first); free(fill); return -1; }
+        first[niche[i] + 1]++;
+        ++nl;
+    }
+    for (int j = 0; j < H; ++j) first[j + 1] += first[j];
+    dkey_t *cand = (dkey_t *)malloc(sizeof(dkey_t) * (size_t)(nl > 0 ? nl : 1));
+    if (!cand) { free(first); free(fill); return -1; }
+    for (int64_t i = 0; i < N; ++i) {
+        if (rank[i] != l) continue;
+        dkey_t *c = &cand[first[niche[i]] + fill[niche[i]]++];
+        c->d = dist[i];
+        c->i = i;
+    }
+    for (int j = 0; j < H; ++j)
+        qsort(cand + first[j], (size_t)(first[j + 1] - first[j]), sizeof(dkey_t), cmp_dkey);
+    free(fill);
+    *cand_out = cand;
+    *first_out = first;
+    return nl;
+}
+
 int oracle_niching(const int32_t *rank, const int32_t *niche, const double *dist, int64_t N,
                    int32_t l, int H, int64_t R, const int32_t *rho_in, uint8_t *chosen)
 {
     if (!rank || !niche || !dist || !rho_in || !chosen || N < 1 || H < 1 || R < 0) return OR_EINVAL;
-    int64_t *cnt = (int64_t *)calloc((size_t)H, sizeof(int64_t));
-    int64_t *start = (int64_t *)calloc((size_t)H + 1, sizeof(int64_t));
-    int64_t *head = (int64_t *)calloc((size_t)H, sizeof(int64_t));
-    int64_t *rho = (int64_t *)calloc((size_t)H, sizeof(int64_t));
-    char *active = (char *)calloc((size_t)H, 1);
-    int64_t nl = 0;
-    for (int64_t i = 0; i < N; ++i) if (rank[i] == l) ++nl;
-    dkey_t *cand = (dkey_t *)malloc(sizeof(dkey_t) * (size_t)(nl > 0 ? nl : 1));
-    if (!cnt || !start || !head || !rho || !active || !cand) {
-        free(cnt); free(start); free(head); free(rho); free(active); free(cand);
-        return OR_EINVAL;
-    }
+    dkey_t *cand = NULL;
+    int64_t *first = NULL;
+    const int64_t nl = group_last_front(rank, niche, dist, N, l, H, &cand, &first);
+    if (nl < 0) return OR_EINVAL;
+    int64_t *used = (int64_t *)calloc((size_t)H, sizeof(int64_t));  /* admitted per reference */
+    int64_t *rho = (int64_t *)malloc(sizeof(int64_t) * (size_t)H);
+    if (!used || !rho || R > nl) { free(cand); free(first); free(used); free(rho); return OR_EINVAL; }
+    for (int j = 0; j < H; ++j) rho[j] = rho_in[j];
     memset(chosen, 0, (size_t)N);
-    for (int64_t i = 0; i < N; ++i)
-        if (rank[i] == l) {
-            if (niche[i] < 0 || niche[i] >= H) { nl = -1; break; }
-            cnt[niche[i]]++;
+    for (int64_t admitted = 0; admitted < R; ++admitted) {
+        int jmin = -1;
+        for (int j = 0; j < H; ++j) {
+            const int has_members = used[j] < first[j + 1] - first[j];
+            if (has_members && (jmin < 0 || rho[j] < rho[jmin])) jmin = j;
         }
-    if (nl < 0 || R > nl) {
-        free(cnt); free(start); free(head); free(rho); free(active); free(cand);
-        return OR_EINVAL;
+        /* R <= |F_l| guarantees some reference still has members */
+        chosen[cand[first[jmin] + used[jmin]].i] = 1;
+        used[jmin]++;
+        rho[jmin]++;
     }
-    for (int j = 0; j < H; ++j) start[j + 1] = start[j] + cnt[j];
-    for (int j = 0; j < H; ++j) head[j] = start[j];
-    for (int64_t i = 0; i < N; ++i)
-        if (rank[i] == l) {
-            int32_t j = niche[i];
-            cand[head[j]].d = dist[i];
-            cand[head[j]].i = i;
-            head[j]++;
+    free(cand); free(first); free(used); free(rho);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One-shot niche selection of the tensorized algorithm (Sec. IV-A.5; the     */
+/* niche-selection steps of Alg. S.4 and Alg. S.6), which the paper offers as */
+/* a parallel approximation of the loop above.  Reading of its steps:         */
+/*   E = references with rho_j = 0 (no admitted member) that have at least   */
+/*       one F_l member (the others are masked with infinity);               */
+/*   every j in E picks its closest F_l member (smallest distance, lowest    */
+/*       index on ties: the argmin over the match matrix);                   */
+/*   n_dif = R - |E|;                                                         */
+/*   n_dif > 0: the n_dif lowest-index unpicked F_l members are added        */
+/*       (the ascending sort of the remaining last-front indices);           */
+/*   n_dif < 0: the |n_dif| picks with the highest indices are dropped, i.e. */
+/*       the R lowest-index picks are kept.                                  */
+/* On the shuffled population the algorithm takes as input, index order is a */
+/* random order, so both fill rules are the paper's random choices.           */
+/* chosen[i] = 1 for the R admitted members; *n_empty (optional) = |E|.       */
+/* ------------------------------------------------------------------------ */
+int oracle_niching_oneshot(const int32_t *rank, const int32_t *niche, const double *dist,
+                           int64_t N, int32_t l, int H, int64_t R, const int32_t *rho_in,
+                           uint8_t *chosen, int64_t *n_empty)
+{
+    if (!rank || !niche || !dist || !rho_in || !chosen || N < 1 || H < 1 || R < 0) return OR_EINVAL;
+    dkey_t *cand = NULL;
+    int64_t *first = NULL;
+    const int64_t nl = group_last_front(rank, niche, dist, N, l, H, &cand, &first);
+    if (nl < 0) return OR_EINVAL;
+    if (R > nl) { free(cand); free(first); return OR_EINVAL; }
+    memset(chosen, 0, (size_t)N);
+    int64_t ne = 0;
+    for (int j = 0; j < H; ++j)
+        if (rho_in[j] == 0 && first[j + 1] > first[j]) {
+            chosen[cand[first[j]].i] = 1;          /* closest member of an empty niche */
+            ++ne;
         }
-    for (int j = 0; j < H; ++j) {
-        qsort(cand + start[j], (size_t)cnt[j], sizeof(dkey_t), cmp_dkey);
-        head[j] = start[j];
-        rho[j] = rho_in[j];
-        active[j] = 1;
+    int64_t ndif = R - ne;
+    if (ndif > 0) {
+        for (int64_t i = 0; i < N && ndif > 0; ++i)
+            if (rank[i] == l && !chosen[i]) { chosen[i] = 1; --ndif; }
+    } else if (ndif < 0) {
+        for (int64_t i = N - 1; i >= 0 && ndif < 0; --i)
+            if (chosen[i]) { chosen[i] = 0; ++ndif; }
     }
-    int64_t taken = 0;
-    while (taken < R) {
-        int jbest = -1;
-        for (int j = 0; j < H; ++j)
-            if (active[j] && (jbest < 0 || rho[j] < rho[jbest])) jbest = j;
-        if (jbest < 0) break; /* cannot happen when R <= |F_l| */
-        if (head[jbest] == start[jbest + 1]) { active[jbest] = 0; continue; }
-        chosen[cand[head[jbest]].i] = 1;
-        head[jbest]++;
-        rho[jbest]++;
-        ++taken;
-    }
-    free(cnt); free(start); free(head); free(rho); free(active); free(cand);
-    return taken == R ? OR_OK : OR_EINVAL;
+    if (n_empty) *n_empty = ne;
+    free(cand); free(first);
+    return OR_OK;
 }
 
 /* ------------------------------------------------------------------------ */
 /* Whole selection (Alg. S.1, outputs as Eq. (13): ascending indices).        */
+/* niching: 0 the loop of Alg. S.1, 1 the one-shot form of Alg. S.4.         */
 /* Outputs may be NULL except selected.  info6 (optional):                   */
 /* [l, num_fronts, |F_l|, R, fallback, near_ties (gap < 1e-6)].               */
 /* ------------------------------------------------------------------------ */
-int oracle_select(const float *objs, int64_t N, int M, const float *refs, int H, int64_t K,
-                  int32_t *selected, int32_t *rank_out, int32_t *niche_out, double *dist_out,
-                  int32_t *dom_in, int32_t *dom_out, int64_t *info6)
+int oracle_select_mode(const float *objs, int64_t N, int M, const float *refs, int H, int64_t K,
+                       int niching, int32_t *selected, int32_t *rank_out, int32_t *niche_out,
+                       double *dist_out, int32_t *dom_in, int32_t *dom_out, int64_t *info6)
 {
+    if (niching != 0 && niching != 1) return OR_EINVAL;
     if (!objs || !refs || !selected || N < 1 || M < 2 || M > 16 || H < 1 || H > 65535 ||
         K < 1 || K > N || N > 2147483647LL)
         return OR_EINVAL;
@@ -484,7 +549,10 @@ int oracle_select(const float *objs, int64_t N, int M, const float *refs, int H,
     if (rc) goto done;
     rc = oracle_niche_count(rank, niche, N, l, H, rho);
     if (rc) goto done;
-    rc = oracle_niching(rank, niche, dist, N, l, H, K - nb, rho, chosen);
+    if (niching == 0)
+        rc = oracle_niching(rank, niche, dist, N, l, H, K - nb, rho, chosen);
+    else
+        rc = oracle_niching_oneshot(rank, niche, dist, N, l, H, K - nb, rho, chosen, NULL);
     if (rc) goto done;
     int64_t t = 0;
     for (int64_t i = 0; i < N; ++i)
@@ -502,6 +570,14 @@ int oracle_select(const float *objs, int64_t N, int M, const float *refs, int H,
 done:
     free(rank); free(niche); free(dist); free(gap); free(rho); free(chosen);
     return rc;
+}
+
+int oracle_select(const float *objs, int64_t N, int M, const float *refs, int H, int64_t K,
+                  int32_t *selected, int32_t *rank_out, int32_t *niche_out, double *dist_out,
+                  int32_t *dom_in, int32_t *dom_out, int64_t *info6)
+{
+    return oracle_select_mode(objs, N, M, refs, H, K, 0, selected, rank_out, niche_out, dist_out,
+                              dom_in, dom_out, info6);
 }
 
 int oracle_num_threads(void)

@@ -414,3 +414,139 @@ def test_select_rejects_bad_arguments(oracle_mod):
         oracle_mod.select(bad, w.refs, w.K)
     with pytest.raises(oracle_mod.OracleError):
         oracle_mod.select(w.objs[:, :1], w.refs[:, :1], 10)         # M = 1
+
+
+# ---------------------------------------------------------------------------
+# Near-tie gap of the association (the quantity that exempts a point from the
+# exact niche comparison): top two distances over every reference
+# ---------------------------------------------------------------------------
+def _numpy_top_two(fp, refs):
+    """Residual distances of every row to every reference line (NumPy), and
+    the relative gap (d2 - d1) / d2 of the two smallest."""
+    rh = refs.astype(np.float64) / np.linalg.norm(refs.astype(np.float64), axis=1, keepdims=True)
+    s = fp @ rh.T
+    res = np.linalg.norm(fp[:, None, :] - s[:, :, None] * rh[None, :, :], axis=2)
+    if res.shape[1] == 1:
+        return res, np.full(res.shape[0], np.inf)
+    two = np.partition(res, 1, axis=1)[:, :2]
+    return res, (two[:, 1] - two[:, 0]) / np.maximum(two[:, 1], 1e-300)
+
+
+@pytest.mark.parametrize("name,N", [("small", 200), ("ties", 2000), ("large", 1500), ("many", 1200)])
+def test_gap_matches_top_two_over_all_references(oracle_mod, name, N):
+    w = workloads.make(name, N=N)
+    r, _ = oracle_mod.ranks(w.objs)
+    l, _, _ = oracle_mod.last_front(r, w.K)
+    nz = oracle_mod.normalize(w.objs, r, l)
+    niche, dist, gap = oracle_mod.associate(w.objs, r, l, nz.z, nz.a, w.refs)
+    S = r <= l
+    fp = (w.objs.astype(np.float64)[S] - nz.z) / nz.a
+    res, g = _numpy_top_two(fp, w.refs)
+    np.testing.assert_allclose(gap[S], g, rtol=0, atol=1e-9)
+    assert np.all(gap[~S] == -1.0)
+    clear = g > 1e-9
+    assert np.all(np.argmin(res, axis=1)[clear] == niche[S][clear])
+    # the oracle's near-tie count is the number of admitted points under 1e-6
+    s = oracle_mod.select(w.objs, w.refs, w.K)
+    assert s.near_ties == int(np.sum(gap[S] < 1e-6))
+
+
+def test_gap_single_reference_and_exact_ties(oracle_mod):
+    # M = 2, references along the axes: every point on the diagonal is exactly
+    # as far from both lines (d = its coordinate), so the gap is exactly 0 and
+    # the lower reference index wins; the ideal point itself (f' = 0) ties too.
+    # The vertices (0,1) and (1,0) make z = 0 and a = 1, so f' = f.
+    F = np.asarray([[0, 1], [1, 0], [0.25, 0.25], [0.5, 0.5], [0.375, 0.125], [0.125, 0.375],
+                    [0.75, 0.75]], np.float32)
+    refs = np.asarray([[1, 0], [0, 1]], np.float32)
+    r, _ = oracle_mod.ranks(F)
+    assert r.tolist() == [0, 0, 0, 1, 0, 0, 2]
+    nz = oracle_mod.normalize(F, r, 2)
+    assert nz.z.tolist() == [0.0, 0.0] and nz.a.tolist() == [1.0, 1.0]
+    niche, dist, gap = oracle_mod.associate(F, r, 2, nz.z, nz.a, refs)
+    for i in (2, 3, 6):
+        assert gap[i] == 0.0 and niche[i] == 0 and dist[i] == float(F[i, 0])
+    assert niche[4] == 0 and dist[4] == 0.125 and gap[4] == pytest.approx(2.0 / 3.0, abs=1e-15)
+    assert niche[5] == 1 and dist[5] == 0.125
+    assert niche[0] == 1 and niche[1] == 0 and gap[0] == 1.0 and gap[1] == 1.0
+    one = refs[:1]
+    _, _, g1 = oracle_mod.associate(F, r, 2, nz.z, nz.a, one)
+    assert np.all(np.isinf(g1))
+    s = oracle_mod.select(F, refs, 6)                # l = 1: S = {r <= 1} holds points 2 and 3
+    assert s.last_front == 1 and s.near_ties == 2
+
+
+# ---------------------------------------------------------------------------
+# One-shot niche selection (Sec. IV-A.5, Alg. S.4, Alg. S.6)
+# ---------------------------------------------------------------------------
+def _oneshot_golden():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oneshot_niching.json")) as fh:
+        return json.load(fh)
+
+
+def test_oneshot_hand_worked(oracle_mod):
+    c = _oneshot_golden()
+    rank = np.asarray(c["rank"], np.int32)
+    niche = np.asarray(c["niche"], np.int32)
+    dist = np.asarray(c["dist"], np.float64)
+    rho = oracle_mod.niche_count(rank, niche, c["l"], c["H"])
+    assert rho.tolist() == c["rho"]
+    for R, want in c["oneshot"].items():
+        got, ne = oracle_mod.niching_oneshot(rank, niche, dist, c["l"], c["H"], int(R), rho)
+        assert np.nonzero(got)[0].tolist() == want and ne == c["n_empty"]
+    for R, want in c["exact"].items():
+        got = oracle_mod.niching(rank, niche, dist, c["l"], c["H"], int(R), rho)
+        assert np.nonzero(got)[0].tolist() == want
+
+
+def _random_niching_case(rng):
+    N = int(rng.integers(5, 300))
+    H = int(rng.integers(1, 16))
+    rank = rng.integers(0, 3, size=N).astype(np.int32)
+    l = 1
+    if not np.any(rank == l):
+        rank[0] = l
+    niche = rng.integers(0, H, size=N).astype(np.int32)
+    niche[rank > l] = -1
+    dist = np.round(rng.uniform(0, 1, size=N), 2)
+    return rank, niche, dist, l, H
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_oneshot_against_loop_and_rules(oracle_mod, seed):
+    rng = np.random.default_rng(500 + seed)
+    rank, niche, dist, l, H = _random_niching_case(rng)
+    rho = oracle_mod.niche_count(rank, niche, l, H)
+    Fl = np.nonzero(rank == l)[0]
+    # closest member (distance, index) of every reference with rho = 0 and members
+    closest = []
+    for j in range(H):
+        m = [i for i in Fl if niche[i] == j]
+        if rho[j] == 0 and m:
+            closest.append(min(m, key=lambda i: (dist[i], i)))
+    closest = sorted(closest)
+    for R in sorted({1, len(Fl), max(1, len(closest)), max(1, len(Fl) // 2)}):
+        got, ne = oracle_mod.niching_oneshot(rank, niche, dist, l, H, R, rho)
+        assert ne == len(closest)
+        assert got.sum() == R and np.all(rank[got] == l)
+        sel = np.nonzero(got)[0].tolist()
+        if R == len(closest):
+            # every empty niche admits its closest member first in the loop too
+            assert got.tolist() == oracle_mod.niching(rank, niche, dist, l, H, R, rho).tolist()
+            assert got.tolist() == bf.keysort_niching(rank, niche, dist, l, rho, R).tolist()
+        if R <= len(closest):
+            assert sel == closest[:R]
+        else:
+            rest = [i for i in Fl if i not in closest]
+            assert sel == sorted(closest + rest[:R - len(closest)])
+
+
+def test_oneshot_whole_selection(oracle_mod):
+    w = workloads.make("ties", N=3000)
+    a = oracle_mod.select(w.objs, w.refs, w.K)
+    b = oracle_mod.select(w.objs, w.refs, w.K, niching="oneshot")
+    assert b.rank.tolist() == a.rank.tolist() and b.niche.tolist() == a.niche.tolist()
+    l = a.last_front
+    assert np.all(np.isin(np.nonzero(a.rank < l)[0], b.selected))
+    assert b.selected.size == w.K and np.all(np.diff(b.selected) > 0)
+    assert np.all(b.rank[b.selected] <= l)
