@@ -5,18 +5,25 @@ One step = one nsga3_select call (every stage: keys and presort, dominance
 counts, front peeling, normalisation, association, niche selection) over the
 large workload (N=200,000 merged points, M=5 objectives, H=210 Das-Dennis
 directions (p=6), K=100,000; sphere shell f = r*u, r = 1 + Exp(rate 4), 20% of
-points with r = 1), inputs resident in device memory.
+points with r = 1), inputs resident in device memory.  The timed loop records
+no per-phase events; phase times come from a separate loop with the library's
+phase events on.
 
 Prints one JSON line (rank 0, N=1).  The roofline object covers the dominant
-phase (the dominance counts: block-table build, in-degree and out-degree
-kernels): algorithmic work M*N*(N-1)/2 pair-objective compares per launch
-(every unordered pair decided once) divided by the phase's duration from HIP
-events the library records on its stream, against the vector-ALU compare
-peak 256 CUs x 64 lanes x 2.4 GHz; traffic is the phase's HBM bytes from
-FETCH_SIZE / WRITE_SIZE counters (profiles/dominance_count_large_traffic.json).
-The "batched" object times 512 selections of mixed N and M in one graph
-launch.  The CPU baseline is the float64 oracle on a bounded sample of the
-same recipe, scaled to N=200,000 by the O(N^2) cost of its dominance stages.
+phase (the dominance counts): algorithmic work M*N*(N-1)/2 pair-objective
+compares per launch (every unordered pair decided once) divided by the phase's
+event-timed duration, against the vector-ALU rate 256 CUs x 64 lanes x 2.4 GHz.
+The block-bitset kernels decide 64 pairs per probe, so this is an effective
+pair-decision rate, not a VALU utilisation, and it can exceed 1.  traffic is
+the phase's HBM bytes from FETCH_SIZE / WRITE_SIZE counters
+(profiles/dominance_count_large_traffic.json).
+
+The float64 oracle runs once on the whole workload: its wall time is the
+cpu_baseline, and its outputs are compared element by element with the timed
+selection ("parity": mismatch counts, all must be 0).  "c5" runs the
+many-objective workload (N=100,000, M=10, H=275) with float32 and bfloat16
+association screening against the oracle; "batched" times 512 selections of
+mixed N and M in one graph launch.
 """
 from __future__ import annotations
 
@@ -41,14 +48,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large", choices=["large", "many", "ties", "small"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-n", type=int, default=140000)
-    ap.add_argument("--check", action="store_true", help="verify one timed result (sampled)")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle (cpu_baseline and parity objects)")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the many-objective float32 / bfloat16 comparison")
     ap.add_argument("--assoc", default="fp32", choices=["fp32", "bf16"],
                     help="association screening precision (re-scoring is float64 in both)")
-    ap.add_argument("--precision-report", action="store_true",
-                    help="instead of the throughput line: float32 vs bfloat16 association on the "
-                         "workload, errors against the float64 oracle and the phase times")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched measurement (512 selections in one graph launch)")
     ap.add_argument("--batch", type=int, default=512, help="instances in the batched plan")
@@ -64,86 +69,157 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(name: str, N_full: int, n_sample: int):
-    """Times the oracle on N=n_sample points of the same recipe and scales the
-    time by (N_full / n_sample)^2 (its dominance count and peeling are O(N^2))."""
+def cpu_baseline(w):
+    """The float64 oracle on the whole workload, once, with every host core;
+    plus one-thread timings of the small (N=200) and ties (N=20,000) workloads.
+    Returns (baseline object, oracle selection)."""
     import oracle
     import workloads
-    w = workloads.make(name, N=n_sample)
     oracle.lib()
     t0 = time.perf_counter()
-    oracle.select(w.objs, w.refs, w.K, with_counts=True)
+    ref = oracle.select(w.objs, w.refs, w.K, with_counts=True)
     dt = time.perf_counter() - t0
-    t_full = dt * (N_full / n_sample) ** 2
+    cores = oracle.num_threads()
+    single = {}
+    oracle.set_num_threads(1)
+    try:
+        for name, reps in (("small", 3), ("ties", 1)):
+            s = workloads.make(name)
+            ts = []
+            for _ in range(reps):
+                t1 = time.perf_counter()
+                oracle.select(s.objs, s.refs, s.K, with_counts=True)
+                ts.append(time.perf_counter() - t1)
+            t = sorted(ts)[len(ts) // 2]
+            single[name] = {"N": s.N, "M": s.M, "s_per_selection": t, "points_per_s": s.N / t}
+    finally:
+        oracle.set_num_threads(0)
     return {
-        "value": N_full / t_full,
+        "value": w.N / dt,
         "unit": "points/s",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
-        "sample": (f"float64 C oracle (OpenMP) on the first-recipe sample N={n_sample} of workload "
-                   f"'{name}' (same seed and shape recipe): {dt:.2f} s; scaled by (N/n)^2 to "
-                   f"N={N_full}: {t_full:.1f} s per selection"),
+        "sample": (f"float64 C oracle (OpenMP, {cores} threads) once on the whole workload "
+                   f"(N={w.N}, M={w.M}, H={w.H}, K={w.K}; ranks, both dominance counts, "
+                   f"selection): {dt:.2f} s"),
+        "single_thread": single,
+    }, ref
+
+
+def parity(w, g, ref):
+    """Mismatch counts of a GPU selection against the oracle's (ranks, counts,
+    selection and front statistics exact; reference lines exact outside the
+    oracle's near-ties; distances within 1e-5 * max(1, ||f'||))."""
+    import numpy as np
+
+    import oracle
+    l = ref.last_front
+    nz = oracle.normalize(w.objs, ref.rank, l)
+    niche, dist, gap = oracle.associate(w.objs, ref.rank, l, nz.z, nz.a, w.refs)
+    S = ref.rank <= l
+    tie = S & (gap < 1e-6)
+    fpn = np.linalg.norm((w.objs.astype(np.float64) - nz.z) / nz.a, axis=1)
+    gd = g["dist"].astype(np.float64)
+    derr = np.abs(gd - dist)
+    info = g["info"]
+    out = {
+        "rank": int(np.sum(g["rank"] != ref.rank)),
+        "selected": int(np.setxor1d(g["selected"], ref.selected).size),
+        "niche_outside_ties": int(np.sum((g["niche"] != niche) & S & ~tie)),
+        "dist_outside_tol": int(np.sum(S & ~tie & (derr > 1e-5 * np.maximum(1.0, fpn)))
+                                + np.sum(~S & (gd != -1.0))),
+        "max_abs_dist_err": float(derr[S & ~tie].max()) if np.any(S & ~tie) else 0.0,
+        "front_stats": int((info.last_front, info.num_fronts, info.last_front_size,
+                            info.num_from_last, info.intercept_fallback) !=
+                           (ref.last_front, ref.num_fronts, ref.last_front_size,
+                            ref.num_from_last, ref.intercept_fallback)),
+        "near_ties": int(tie.sum()),
     }
+    if g.get("dom_in") is not None:
+        out["dom_in"] = int(np.sum(g["dom_in"] != ref.dom_in))
+        out["dom_out"] = int(np.sum(g["dom_out"] != ref.dom_out))
+    return out
 
 
-def precision_report(args, w, objs, refs):
-    """One JSON line: association error of each screening precision against the
-    float64 oracle (on the GPU's own ranks, which both modes share), selection
-    agreement between the modes, and the association phase time of each."""
+def _host(res):
+    return {"selected": res.selected.cpu().numpy(), "rank": res.rank.cpu().numpy(),
+            "niche": res.niche.cpu().numpy(), "dist": res.dist.cpu().numpy(),
+            "dom_in": None if res.dom_in is None else res.dom_in.cpu().numpy(),
+            "dom_out": None if res.dom_out is None else res.dom_out.cpu().numpy(),
+            "info": res.info()}
+
+
+def _time_calls(fn, steps, stream):
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def _phase_pass(ctx, fn, steps):
+    """Phase times (ms per call) from the library's HIP events, in a loop of
+    its own so that the headline loop records none."""
+    import torch
+
+    import paper_2503_20286_amd as nsga3
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    ms, calls = ctx.phase_times()
+    ctx.profile(False)
+    return {name: ms[q] / max(calls, 1) for q, name in enumerate(nsga3.PHASES)}
+
+
+def c5_report(args):
+    """Many-objective workload with float32 and bfloat16 association
+    screening: whole-selection and association times, and each mode's
+    association and selection against the float64 oracle."""
     import numpy as np
     import torch
 
     import oracle
     import paper_2503_20286_amd as nsga3
-    modes = {"fp32": nsga3.ASSOC_FP32, "bf16": nsga3.ASSOC_BF16}
-    out = {}
-    res = {}
-    for name, mode in modes.items():
+    import workloads
+    w = workloads.make("many")
+    objs = torch.from_numpy(w.objs).cuda()
+    refs = torch.from_numpy(w.refs).cuda()
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    ref = oracle.select(w.objs, w.refs, w.K, with_counts=False)
+    t_oracle = time.perf_counter() - t0
+    out = {"workload": f"many: N={w.N} M={w.M} H={w.H} K={w.K}",
+           "oracle_s_without_counts": t_oracle}
+    sel = {}
+    for name, mode in (("fp32", nsga3.ASSOC_FP32), ("bf16", nsga3.ASSOC_BF16)):
         ctx = nsga3.Context(0, assoc=mode)
         ctx.reserve(w.N, w.M, w.H)
-        r = nsga3.select(objs, refs, w.K, ctx=ctx)
+        r = nsga3.select(objs, refs, w.K, ctx=ctx, want_counts=False)
+
+        def call():
+            nsga3.select(objs, refs, w.K, ctx=ctx, out=r, want_counts=False)
         for _ in range(args.warmup):
-            nsga3.select(objs, refs, w.K, ctx=ctx, out=r)
-        torch.cuda.synchronize()
-        ctx.profile(True)
-        for _ in range(args.steps):
-            nsga3.select(objs, refs, w.K, ctx=ctx, out=r)
-        torch.cuda.synchronize()
-        ms, calls = ctx.phase_times()
-        ctx.profile(False)
-        res[name] = {k: getattr(r, k).cpu().numpy() for k in ("selected", "rank", "niche", "dist")}
-        res[name]["info"] = r.info()
-        out[name] = {"associate_ms": ms[4] / calls, "total_ms": sum(ms) / calls}
+            call()
+        ms = _time_calls(call, args.steps, stream)
+        ph = _phase_pass(ctx, call, args.steps)
+        g = _host(r)
+        sel[name] = g["selected"]
+        p = parity(w, g, ref)
+        out[name] = {"ms_per_selection": ms, "associate_ms": ph["associate"],
+                     "niche_mismatch_outside_ties": p["niche_outside_ties"],
+                     "max_abs_dist_err": p["max_abs_dist_err"],
+                     "rank_mismatch": p["rank"], "selected_mismatch": p["selected"],
+                     "oracle_near_ties": p["near_ties"]}
         ctx.close()
-    rank = res["fp32"]["rank"]
-    assert np.array_equal(rank, res["bf16"]["rank"])
-    l = res["fp32"]["info"].last_front
-    nz = oracle.normalize(w.objs, rank, l)
-    niche, dist, gap = oracle.associate(w.objs, rank, l, nz.z, nz.a, w.refs)
-    S = rank <= l
-    tie = S & (gap < 1e-6)
-    fpn = np.linalg.norm((w.objs.astype(np.float64) - nz.z) / nz.a, axis=1)
-    for name in modes:
-        g = res[name]
-        mism = (g["niche"] != niche) & S
-        dd = np.abs(g["dist"].astype(np.float64) - dist)[S]
-        out[name].update({
-            "niche_mismatch_outside_ties": int(np.sum(mism & ~tie)),
-            "niche_mismatch_at_ties": int(np.sum(mism & tie)),
-            "max_abs_dist_err": float(dd.max()),
-            "max_rel_dist_err": float((dd / np.maximum(1.0, fpn[S])).max()),
-            "near_ties_reported": g["info"].near_ties,
-        })
-    line = {
-        "metric": "association error vs float64 oracle, float32 and bfloat16 screening",
-        "workload": f"{args.workload}: N={w.N} M={w.M} H={w.H} K={w.K}",
-        "admitted_points": int(S.sum()),
-        "oracle_near_ties": int(tie.sum()),
-        "selection_identical_across_modes": bool(np.array_equal(res["fp32"]["selected"],
-                                                                res["bf16"]["selected"])),
-        "modes": out,
-    }
-    print(json.dumps(line), flush=True)
+    out["selection_identical_across_modes"] = bool(np.array_equal(sel["fp32"], sel["bf16"]))
+    return out
 
 
 def batched(args):
@@ -189,8 +265,9 @@ def batched(args):
     stop.record(stream)
     torch.cuda.synchronize()
     ms_single = start.elapsed_time(stop)
-    same = all(torch.equal(a.selected, b.selected) and torch.equal(a.rank, b.rank)
-               for a, b in zip(plan.results, outs))
+    fields = ("selected", "rank", "niche", "dist", "dom_in", "dom_out")
+    same = all(torch.equal(getattr(a, k), getattr(b, k)) for a, b in zip(plan.results, outs)
+               for k in fields) and all(a.info() == b.info() for a, b in zip(plan.results, outs))
     info = plan.info()
     plan.close()
     tuned = ctx.tuned_shapes()
@@ -286,9 +363,6 @@ def main():
     dev = torch.device("cuda:0")
     objs = torch.from_numpy(w.objs).to(dev)
     refs = torch.from_numpy(w.refs).to(dev)
-    if args.precision_report:
-        precision_report(args, w, objs, refs)
-        return
     ctx = nsga3.Context(0, assoc=nsga3.ASSOC_BF16 if args.assoc == "bf16" else nsga3.ASSOC_FP32)
     ctx.reserve(w.N, w.M, w.H)
     stream = torch.cuda.current_stream(dev)
@@ -300,30 +374,14 @@ def main():
     if info.status != 0:
         raise SystemExit(f"selection reported status {info.status}")
 
-    ctx.profile(True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_host = time.perf_counter()
-    start.record(stream)
-    for _ in range(args.steps):
+    def call():
         nsga3.select(objs, refs, w.K, ctx=ctx, out=out)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    t_host = time.perf_counter() - t_host
-    ms_total = start.elapsed_time(stop)
-    phase_ms, calls = ctx.phase_times()
-    ctx.profile(False)
-    ms_per_step = ms_total / args.steps
-    phases = {name: phase_ms[q] / max(calls, 1) for q, name in enumerate(nsga3.PHASES)}
 
-    if args.check:
-        import oracle
-        sel = out.selected.cpu().numpy()
-        rank = out.rank.cpu().numpy()
-        l, nb, nl = oracle.last_front(rank, w.K)
-        assert sel.size == w.K and np.all(np.diff(sel) > 0)
-        assert np.all(rank[sel] <= l)
+    t_host = time.perf_counter()
+    ms_per_step = _time_calls(call, args.steps, stream)
+    t_host = time.perf_counter() - t_host
+    phases = _phase_pass(ctx, call, args.steps)
+    g = _host(out)
 
     N, M = w.N, w.M
     cmp_per_launch = M * N * (N - 1) / 2.0
@@ -366,10 +424,19 @@ def main():
             "traffic": traffic,
             "work_per_launch": f"{cmp_per_launch:.4e} pair-objective compares (M*N*(N-1)/2: every "
                                "unordered pair decided once)",
+            "note": "effective pair-decision rate: one block-bitset probe decides 64 pairs with "
+                    "M key searches and M mask ANDs, so frac is not a VALU utilisation and can "
+                    "exceed 1",
             "frac_counts_and_peeling": cmp_per_launch / ((phases["dominance_count"] + phases["peel"])
                                                           / 1e3) / PEAK_CMP_PER_S,
         },
         "phases_ms": phases,
+        "streaming_phases_gb_s": {
+            # algorithmic HBM bytes of the streaming phases over their event time
+            "prep_sort": N * M * 4 / (phases["prep_sort"] * 1e6),
+            "associate": (N * M * 4 + w.H * M * 4 + 8 * N) / (phases["associate"] * 1e6),
+            "niching_and_output": (w.K + 3 * N) * 4 / (phases["niching"] * 1e6),
+        },
         "fronts": {"num_fronts": info.num_fronts, "last_front": info.last_front,
                    "last_front_size": info.last_front_size, "num_from_last": info.num_from_last,
                    "near_ties": info.near_ties, "intercept_fallback": info.intercept_fallback},
@@ -378,7 +445,10 @@ def main():
     if not args.no_batch:
         res["batched"] = batched(args)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args.workload, N, min(args.cpu_sample_n, N))
+        res["cpu_baseline"], ref = cpu_baseline(w)
+        res["parity"] = parity(w, g, ref)
+    if not args.no_c5 and args.workload == "large":
+        res["c5"] = c5_report(args)
     print(json.dumps(res), flush=True)
 
 

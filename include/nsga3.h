@@ -74,9 +74,13 @@ typedef struct {
     int32_t last_front_size;      /* |F_l| */
     int32_t num_from_last;        /* R = K - #{rank < l}: members picked from F_l */
     int32_t intercept_fallback;   /* 0 hyperplane, 1 nadir, 2 nadir with a zero axis set to 1 */
-    int32_t near_ties;            /* admitted points whose two closest reference lines are
-                                     within 1e-6 relative distance (float64 re-scoring) */
-    int32_t reserved;
+    int32_t near_ties;            /* admitted points whose two closest reference lines among
+                                     the candidates that survive screening are within 1e-6
+                                     relative distance after float64 re-scoring.  A line
+                                     screened out is never counted, so this is a lower bound
+                                     on the number over all H lines (diagnostic only). */
+    int32_t reserved;             /* device error bits of the last failing check (diagnostic;
+                                     0 when status is NSGA3_OK) */
 } nsga3_info;
 
 typedef struct nsga3_ctx nsga3_ctx;

@@ -47,6 +47,8 @@ def _declare(L):
     L.oracle_select.argtypes = [P, i64, i32, P, i32, i64, P, P, P, P, P, P, P]
     L.oracle_select_mode.argtypes = [P, i64, i32, P, i32, i64, i32, P, P, P, P, P, P, P]
     L.oracle_num_threads.argtypes = []
+    L.oracle_set_num_threads.argtypes = [i32]
+    L.oracle_set_num_threads.restype = None
     for name in ("oracle_dominates", "oracle_dominance", "oracle_dominance_one", "oracle_ranks",
                  "oracle_last_front", "oracle_normalize", "oracle_associate",
                  "oracle_niche_count", "oracle_niching", "oracle_niching_oneshot",
@@ -76,6 +78,11 @@ def _objs(objs):
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for later oracle calls from this thread (n < 1: one per core)."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def dominance(objs):

@@ -580,6 +580,17 @@ int oracle_select(const float *objs, int64_t N, int M, const float *refs, int H,
                               dom_in, dom_out, info6);
 }
 
+/* Thread count for later calls from this thread (timing of the one-thread
+ * oracle); n < 1 restores one thread per host core. */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

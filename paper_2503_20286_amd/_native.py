@@ -117,6 +117,16 @@ def version() -> int:
     return int(load().nsga3_version())
 
 
+def workspace_size(N: int, M: int, H: int) -> int:
+    """Bytes of context workspace a single selection of this size needs."""
+    L = load()
+    b = ctypes.c_size_t()
+    rc = L.nsga3_workspace_size(int(N), int(M), int(H), ctypes.byref(b))
+    if rc != 0:
+        raise NativeError("nsga3_workspace_size", rc, L)
+    return int(b.value)
+
+
 def header_symbols():
     """Function names declared by include/nsga3.h."""
     with open(HEADER) as fh:
@@ -292,6 +302,12 @@ def select(objs, refs, K: int, *, ctx: Optional[Context] = None, assoc: int = AS
     if rc != 0:
         raise NativeError("nsga3_select", rc, ctx._lib)
     return out
+
+
+def alloc_outputs(N: int, K: int, device, want_counts: bool = True,
+                  want_dist: bool = True) -> Selection:
+    """Output tensors for one selection of K of N points on ``device``."""
+    return _alloc_outputs(N, K, device, want_counts, want_dist)
 
 
 def _alloc_outputs(N, K, dev, want_counts=True, want_dist=True):

@@ -50,10 +50,12 @@ def line_distance64(objs, z, a, refs, ref_idx):
     return np.sqrt(q)
 
 
-def compare_full(objs, refs, K, g, with_counts=True):
-    """Element-by-element comparison with the oracle's whole selection.
-    Returns a dict of mismatch counts (all must be zero)."""
-    s = oracle.select(objs, refs, K, with_counts=with_counts)
+def compare_full(objs, refs, K, g, with_counts=True, s=None):
+    """Element-by-element comparison with the oracle's whole selection ``s``
+    (computed here when not given).  Returns a dict of mismatch counts (all
+    must be zero) and the number of near-tie points."""
+    if s is None:
+        s = oracle.select(objs, refs, K, with_counts=with_counts)
     rep = {}
     rep["rank"] = int(np.sum(g["rank"] != s.rank))
     if with_counts:
@@ -77,7 +79,7 @@ def compare_full(objs, refs, K, g, with_counts=True):
         ok = np.where(S, dist_close(g["dist"], dist, fpn), g["dist"] == -1.0)
         rep["dist"] = int(np.sum(~ok & ~tie))
     if not np.any(tie):
-        rep["selected"] = int(not np.array_equal(g["selected"], s.selected))
+        rep["selected"] = _sel_mismatch(g["selected"], s.selected)
     else:
         # stage-wise: oracle niching on the GPU's association, with the float64
         # distance of each near-tie point to the reference the GPU chose
@@ -88,6 +90,13 @@ def compare_full(objs, refs, K, g, with_counts=True):
             d64[moved] = line_distance64(objs[moved], nz.z, nz.a, refs, g["niche"][moved])
         chosen = oracle.niching(g["rank"], g["niche"], d64, l, refs.shape[0], s.num_from_last, rho)
         want = np.nonzero((g["rank"] < l) | chosen)[0]
-        rep["selected"] = int(not np.array_equal(g["selected"], want))
+        rep["selected"] = _sel_mismatch(g["selected"], want)
     rep["near_ties"] = int(np.sum(tie))
     return rep
+
+
+def _sel_mismatch(got, want):
+    """Number of indices in one selection and not the other (0 iff equal)."""
+    if got.shape == want.shape and np.array_equal(got, want):
+        return 0
+    return int(np.setxor1d(got, want).size) or 1

@@ -87,6 +87,36 @@ def test_plan_matches_single_calls_and_oracle(plan_mode):
     plan.close()
 
 
+def test_benchmark_batch_against_oracle():
+    """The 512-instance batch the benchmark times (N_b in [200, 20000], M_b in
+    {2, 3, 5}), captured with autotuning as the benchmark does; the largest
+    instance of each objective count and 16 seeded random ones are compared
+    with the oracle element by element."""
+    import torch
+    import paper_2503_20286_amd as nsga3
+    ws = workloads.make_batch(512)
+    probs = _dev(ws)
+    ctx = nsga3.Context(0, autotune=True)
+    ctx.reserve(max(w.N for w in ws), 5, 210)
+    plan = nsga3.Plan(probs, ctx=ctx)
+    for _ in range(2):
+        plan.launch()
+    torch.cuda.synchronize()
+    pick = set()
+    for M in sorted({w.M for w in ws}):
+        pick.add(max((b for b, w in enumerate(ws) if w.M == M), key=lambda b: ws[b].N))
+    pick |= set(np.random.default_rng(512).choice(len(ws), size=16, replace=False).tolist())
+    for b in sorted(pick):
+        w = ws[b]
+        print(f"batch instance {b}: N={w.N} M={w.M} H={w.H} K={w.K}", flush=True)
+        g = _host(plan.results[b])
+        g["info"] = plan.results[b].info()
+        rep = compare_full(w.objs, w.refs, w.K, g)
+        assert not {k: v for k, v in rep.items() if k != "near_ties" and v}, (b, rep)
+    plan.close()
+    ctx.close()
+
+
 def test_plan_replay_with_new_data_in_same_buffers(plan_mode):
     import torch
     import paper_2503_20286_amd as nsga3
