@@ -133,6 +133,30 @@ nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t 
                           hipStream_t stream);
 
 /*
+ * Allocation-free form of nsga3_select, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, outputs and results as nsga3_select with
+ * float32 association screening, on the current HIP device, without a
+ * context.  The workspace is a fixed array of NSGA3_NOALLOC_MAX_WORKSPACE
+ * bytes that every device holds for the life of the process; a call whose
+ * workspace (nsga3_workspace_size) is larger returns NSGA3_E_NOMEM and
+ * enqueues nothing (N = 20,000, M = 3, H = 91 needs 5 MiB; N = 80,000, M = 5,
+ * H = 210 about 30 MiB).  The call allocates nothing and synchronises
+ * nothing: the first call on a device looks up the array's address and the
+ * device's shapes (host queries only).  Every call on a device shares that
+ * device's array: calls that overlap in time on one device (different
+ * streams, or different host threads) race and give undefined results;
+ * calls on one stream are ordered and safe.  Levels beyond the 24th front are
+ * peeled by one work-group (no cooperative launch), so inputs with very many
+ * fronts are slower than with nsga3_select.
+ */
+#define NSGA3_NOALLOC_MAX_WORKSPACE (32u << 20)
+nsga3_status nsga3_select_noalloc(const float *objs, int64_t N, int32_t M, const float *refs,
+                                  int32_t H, int64_t K, int32_t *selected, int32_t *rank,
+                                  int32_t *niche, float *dist, int32_t *dom_in, int32_t *dom_out,
+                                  nsga3_info *info, hipStream_t stream);
+
+/*
  * Batched selections: many independent problems (the islands or restarts of an
  * optimizer farm), each with its own N, M, H and K, run by one graph launch.
  * The fields of nsga3_problem mean what the arguments of nsga3_select mean;

@@ -14,7 +14,7 @@ from __future__ import annotations
 from ._native import (  # noqa: F401
     ASSOC_BF16, ASSOC_FP32, NUM_PHASES, PHASES, Context, Info, NativeError, Plan, Selection, STATUS,
     default_context, exported_symbols, header_symbols, lib_path, load, select, version,
-    workspace_size, alloc_outputs,
+    workspace_size, select_noalloc, alloc_outputs,
 )
 
 __all__ = ["select", "Context", "Plan", "Selection", "Info", "NativeError", "load", "version",

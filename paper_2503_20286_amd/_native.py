@@ -86,6 +86,8 @@ def load():
         L.nsga3_workspace_size.restype = ctypes.c_int
         L.nsga3_select.argtypes = [P, P, i64, i32, P, i32, i64, P, P, P, P, P, P, P, P]
         L.nsga3_select.restype = ctypes.c_int
+        L.nsga3_select_noalloc.argtypes = [P, i64, i32, P, i32, i64, P, P, P, P, P, P, P, P]
+        L.nsga3_select_noalloc.restype = ctypes.c_int
         L.nsga3_status_string.argtypes = [ctypes.c_int]
         L.nsga3_status_string.restype = ctypes.c_char_p
         L.nsga3_profile.argtypes = [P, ctypes.c_int]
@@ -301,6 +303,34 @@ def select(objs, refs, K: int, *, ctx: Optional[Context] = None, assoc: int = AS
                                ctypes.c_void_p(s.cuda_stream))
     if rc != 0:
         raise NativeError("nsga3_select", rc, ctx._lib)
+    return out
+
+
+def select_noalloc(objs, refs, K: int, *, out: Selection, stream=None) -> Selection:
+    """The allocation-free entry point (nsga3_select_noalloc): same results as
+    select() with float32 screening, into the caller's ``out`` buffers (see
+    ``alloc_outputs``), on the current device; the library allocates nothing.
+    Raises NativeError (code NSGA3_E_NOMEM) when the problem's workspace is
+    larger than the library's fixed scratch array."""
+    import torch
+    _check_tensor(objs, "objs", 2)
+    _check_tensor(refs, "refs", 2)
+    N, M = objs.shape
+    H = refs.shape[0]
+    if refs.shape[1] != M:
+        raise ValueError("refs must have M columns")
+    s = stream if stream is not None else torch.cuda.current_stream(objs.device)
+    L = load()
+
+    def p(t):
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+    rc = L.nsga3_select_noalloc(p(objs), int(N), int(M), p(refs), int(H), int(K),
+                                p(out.selected), p(out.rank), p(out.niche), p(out.dist),
+                                p(out.dom_in), p(out.dom_out), p(out.info_raw),
+                                ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise NativeError("nsga3_select_noalloc", rc, L)
     return out
 
 

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -346,6 +347,61 @@ hipError_t enqueue_select(const EnqArgs &a, const nsga3_problem &p, hipStream_t 
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Allocation-free selection.  Its workspace is `scratch`, one array per device
+// in the code object's own memory, so a call allocates nothing (for callers
+// under graph capture or in loops that must not allocate).  In host code the
+// array's name is only a stand-in: its device address is fetched once per
+// device with hipGetSymbolAddress and kept in g_noalloc[device].
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[NSGA3_NOALLOC_MAX_WORKSPACE];
+
+namespace {
+constexpr int kNoallocMaxDevices = 64;
+struct NoallocDevice {
+    bool ready = false;
+    nsga3_status status = NSGA3_OK;   // set-up result, kept for later calls
+    char *scratch = nullptr;          // device address of `scratch` on this device
+    int num_cus = 0;
+    int peel_bpc[17] = {};
+};
+NoallocDevice g_noalloc[kNoallocMaxDevices];
+std::mutex g_noalloc_mu;
+
+// Once per device, with that device current: the array's address and the
+// launch shapes (device queries only).
+nsga3_status noalloc_setup(int dev, NoallocDevice **out) {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    NoallocDevice &d = g_noalloc[dev];
+    if (!d.ready) {
+        d.ready = true;
+        d.status = NSGA3_OK;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            d.status = NSGA3_E_HIP;
+        } else if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            d.status = NSGA3_E_UNSUPPORTED;
+        } else {
+            void *ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+                (void)hipGetLastError();
+                d.status = NSGA3_E_HIP;
+            } else {
+                d.scratch = (char *)ptr;
+                d.num_cus = prop.multiProcessorCount;
+                for (int m = 2; m <= 16; ++m) {
+                    const int nb = peel_max_blocks_per_cu(m);
+                    d.peel_bpc[m] = nb < kMaxPeelBlocksPerCu ? nb : kMaxPeelBlocksPerCu;
+                }
+            }
+        }
+    }
+    *out = &d;
+    return d.status;
+}
+}  // namespace
+
 extern "C" {
 
 const char *nsga3_status_string(nsga3_status s) {
@@ -508,6 +564,36 @@ nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t 
     a.assoc = (int)ctx->opt.assoc;
     a.marks = ctx->profiling ? ctx : nullptr;
     a.last_fronts = ctx->last_fronts;
+    const nsga3_problem p = {objs, N, M, refs, H, K, selected, rank, niche, dist,
+                             dom_in, dom_out, info};
+    return enqueue_select(a, p, stream) == hipSuccess ? NSGA3_OK : NSGA3_E_HIP;
+}
+
+nsga3_status nsga3_select_noalloc(const float *objs, int64_t N, int32_t M, const float *refs,
+                                  int32_t H, int64_t K, int32_t *selected, int32_t *rank,
+                                  int32_t *niche, float *dist, int32_t *dom_in, int32_t *dom_out,
+                                  nsga3_info *info, hipStream_t stream) {
+    if (!objs || !refs || !selected) return NSGA3_E_INVALID;
+    if (!sizes_ok(N, M, H) || K < 1 || K > N) return NSGA3_E_INVALID;
+    const Layout L = layout_for(N, M, H, kGridCap);
+    if (L.total > (size_t)NSGA3_NOALLOC_MAX_WORKSPACE) return NSGA3_E_NOMEM;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); return NSGA3_E_HIP; }
+    if (dev < 0 || dev >= kNoallocMaxDevices) return NSGA3_E_UNSUPPORTED;
+    NoallocDevice *d = nullptr;
+    const nsga3_status st = noalloc_setup(dev, &d);
+    if (st != NSGA3_OK) return st;
+    EnqArgs a;
+    a.ws = d->scratch;
+    a.cfg.num_cus = d->num_cus;
+    a.cfg.peel_blocks_per_cu = d->peel_bpc[M];
+    a.cfg.phase_a_blocks_per_cu = 4;
+    a.cfg.host_levels = kDefaultHostLevels;
+    a.cfg.bitsets = true;
+    a.cfg.tail_block = true;          // no cooperative launch: capture-safe
+    a.assoc = NSGA3_ASSOC_FP32;
+    a.marks = nullptr;
+    a.last_fronts = nullptr;
     const nsga3_problem p = {objs, N, M, refs, H, K, selected, rank, niche, dist,
                              dom_in, dom_out, info};
     return enqueue_select(a, p, stream) == hipSuccess ? NSGA3_OK : NSGA3_E_HIP;
