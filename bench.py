@@ -178,6 +178,49 @@ def _phase_pass(ctx, fn, steps):
     return {name: ms[q] / max(calls, 1) for q, name in enumerate(nsga3.PHASES)}
 
 
+def oneshot_report(args, w, objs, refs, g_exact, ref):
+    """The one-shot niche selection on the same workload: time per selection
+    and of the niching phase, its agreement with the oracle's one-shot form,
+    and the quality delta against the exact loop (selection difference and
+    how many references the selected set covers)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2503_20286_amd as nsga3
+    ctx = nsga3.Context(0, niching=nsga3.NICHING_ONESHOT)
+    ctx.reserve(w.N, w.M, w.H)
+    r = nsga3.select(objs, refs, w.K, ctx=ctx)
+
+    def call():
+        nsga3.select(objs, refs, w.K, ctx=ctx, out=r)
+    for _ in range(args.warmup):
+        call()
+    ms = _time_calls(call, args.steps, torch.cuda.current_stream())
+    ph = _phase_pass(ctx, call, args.steps)
+    g = _host(r)
+    ctx.close()
+    out = {"ms_per_selection": ms, "niching_ms": ph["niching"]}
+    if ref is not None:
+        l = ref.last_front
+        rho = oracle.niche_count(ref.rank, ref.niche, l, w.H)
+        chosen, ne = oracle.niching_oneshot(ref.rank, ref.niche, ref.dist, l, w.H,
+                                            ref.num_from_last, rho)
+        want = np.nonzero((ref.rank < l) | chosen)[0]
+        out["selected_mismatch_vs_oracle_oneshot"] = int(np.setxor1d(g["selected"], want).size)
+        out["empty_niche_picks"] = int(ne)
+    cov = {}
+    for name, x in (("exact", g_exact), ("oneshot", g)):
+        nic = x["niche"][x["selected"]]
+        cnt = np.bincount(nic, minlength=w.H)
+        cov[name] = {"refs_covered": int(np.sum(cnt > 0)), "max_niche_count": int(cnt.max())}
+    out["quality_vs_exact"] = {
+        "selected_differ": int(np.setdiff1d(g["selected"], g_exact["selected"]).size),
+        **{f"{k}_{m}": v for k, d in cov.items() for m, v in d.items()},
+    }
+    return out
+
+
 def c5_report(args):
     """Many-objective workload with float32 and bfloat16 association
     screening: whole-selection and association times, and each mode's
@@ -444,9 +487,11 @@ def main():
     }
     if not args.no_batch:
         res["batched"] = batched(args)
+    ref = None
     if not args.no_cpu_baseline:
         res["cpu_baseline"], ref = cpu_baseline(w)
         res["parity"] = parity(w, g, ref)
+    res["oneshot_niching"] = oneshot_report(args, w, objs, refs, g, ref)
     if not args.no_c5 and args.workload == "large":
         res["c5"] = c5_report(args)
     print(json.dumps(res), flush=True)

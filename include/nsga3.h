@@ -13,7 +13,8 @@
  *   - dominance: Listing 1, Eq. (6); dominance count: Eq. (7)
  *   - fronts: Eq. (8)-(9), Alg. S.3; last front l: end of Sec. IV-A.1
  *   - normalisation: Alg. S.5;  association: Eq. (10);  niche counts: Eq. (11)
- *   - niching: Alg. S.1 (its inner loop);  output indices: Eq. (13)
+ *   - niching: Alg. S.1 (its inner loop), or the one-shot form of Sec. IV-A.5
+ *     (Alg. S.4, Alg. S.6);  output indices: Eq. (13)
  *
  * Conventions shared by all entry points
  *   - All objectives are minimised (Eq. (1)).  Objective matrices are N x M,
@@ -57,6 +58,18 @@ typedef enum {
     NSGA3_ASSOC_BF16 = 1       /* candidate screening in bfloat16 on the matrix cores */
 } nsga3_assoc_mode;
 
+typedef enum {
+    NSGA3_NICHING_EXACT = 0,      /* the niche-preserving loop of Alg. S.1 (one member at a time:
+                                     least-crowded reference first, its closest member) */
+    NSGA3_NICHING_ONESHOT = 1     /* the one-shot tensorized form (Sec. IV-A.5; niche-selection
+                                     steps of Alg. S.4, Alg. S.6): every reference with no admitted
+                                     member and some last-front member admits its closest one at
+                                     once; a shortfall is filled with the lowest-index remaining
+                                     last-front members, a surplus keeps the lowest-index picks
+                                     (index order is the random order of the shuffled population
+                                     the paper takes as input).  An approximation of the loop. */
+} nsga3_niching_mode;
+
 typedef struct {
     nsga3_assoc_mode assoc;       /* default NSGA3_ASSOC_FP32 */
     int32_t autotune;             /* 1: nsga3_plan_create times candidate work-item shapes per
@@ -64,6 +77,8 @@ typedef struct {
                                      fastest (cached in the context); 0: fixed defaults.
                                      Results never depend on the choice. */
     size_t max_workspace_bytes;   /* 0 = no cap */
+    nsga3_niching_mode niching;   /* default NSGA3_NICHING_EXACT.  Batched plans of a context with
+                                     NSGA3_NICHING_ONESHOT run as a graph of single selections. */
 } nsga3_options;
 
 /* Per-call diagnostics, written on-stream into DEVICE memory. */

@@ -23,6 +23,8 @@ NUM_PHASES = 6
 PHASES = ("prep_sort", "dominance_count", "peel", "normalize", "associate", "niching")
 ASSOC_FP32 = 0
 ASSOC_BF16 = 1
+NICHING_EXACT = 0
+NICHING_ONESHOT = 1
 
 
 class NativeError(RuntimeError):
@@ -39,7 +41,7 @@ class NativeError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("assoc", ctypes.c_int), ("autotune", ctypes.c_int32),
-                ("max_workspace_bytes", ctypes.c_size_t)]
+                ("max_workspace_bytes", ctypes.c_size_t), ("niching", ctypes.c_int)]
 
 
 PLAN_STAGES = ("keys_refs", "radix_hist", "radix_scatter", "records", "dominance",
@@ -154,9 +156,9 @@ class Context:
     """Owns an nsga3_ctx (device workspace) on one HIP device."""
 
     def __init__(self, device: int = 0, assoc: int = ASSOC_FP32, max_workspace_bytes: int = 0,
-                 autotune: bool = False):
+                 autotune: bool = False, niching: int = NICHING_EXACT):
         self._lib = load()
-        opt = _Options(assoc, 1 if autotune else 0, max_workspace_bytes)
+        opt = _Options(assoc, 1 if autotune else 0, max_workspace_bytes, niching)
         h = ctypes.c_void_p()
         rc = self._lib.nsga3_create(ctypes.byref(h), int(device), ctypes.byref(opt))
         if rc != 0:
@@ -164,6 +166,7 @@ class Context:
         self._h = h
         self.device = int(device)
         self.assoc = assoc
+        self.niching = niching
 
     @property
     def handle(self):
@@ -216,10 +219,10 @@ class Context:
 _default_ctx: Dict[tuple, Context] = {}
 
 
-def default_context(device: int, assoc: int = ASSOC_FP32) -> Context:
-    key = (device, assoc)
+def default_context(device: int, assoc: int = ASSOC_FP32, niching: int = NICHING_EXACT) -> Context:
+    key = (device, assoc, niching)
     if key not in _default_ctx:
-        _default_ctx[key] = Context(device, assoc)
+        _default_ctx[key] = Context(device, assoc, niching=niching)
     return _default_ctx[key]
 
 
@@ -264,8 +267,8 @@ def _check_tensor(t, name, ndim):
 
 
 def select(objs, refs, K: int, *, ctx: Optional[Context] = None, assoc: int = ASSOC_FP32,
-           want_counts: bool = True, want_dist: bool = True, out: Optional[Selection] = None,
-           stream=None) -> Selection:
+           niching: int = NICHING_EXACT, want_counts: bool = True, want_dist: bool = True,
+           out: Optional[Selection] = None, stream=None) -> Selection:
     """Environmental selection of K of the N rows of ``objs`` (N x M float32,
     minimised) with reference directions ``refs`` (H x M float32).  Returns
     device tensors; the call is asynchronous on the current (or given) stream."""
@@ -280,7 +283,8 @@ def select(objs, refs, K: int, *, ctx: Optional[Context] = None, assoc: int = AS
         raise ValueError("refs must have M columns")
     dev = objs.device
     if ctx is None:
-        ctx = default_context(dev.index if dev.index is not None else torch.cuda.current_device(), assoc)
+        ctx = default_context(dev.index if dev.index is not None else torch.cuda.current_device(),
+                              assoc, niching)
     if out is None:
         i32 = dict(dtype=torch.int32, device=dev)
         out = Selection(

@@ -94,6 +94,8 @@ Layout layout_for(int64_t N, int M, int H, int max_grid) {
     size_t temp = radix_sort_temp_bytes(N);
     const size_t ct = compact_temp_bytes(N);
     if (ct > temp) temp = ct;
+    const size_t ot = oneshot_temp_bytes(N);
+    if (ot > temp) temp = ot;
     const int nparts = normalize_partial_blocks(N);
     L.skey = bump(c, 8 * n);
     L.skey_alt = bump(c, 8 * n);
@@ -228,6 +230,7 @@ struct EnqArgs {
     char *ws;
     LaunchCfg cfg;
     int assoc;
+    int niching = NSGA3_NICHING_EXACT;
     nsga3_ctx *marks;                 // record phase events into this context, or null
     volatile int32_t *last_fronts;    // pinned slot for the front count, or null
 };
@@ -338,6 +341,7 @@ hipError_t enqueue_select(const EnqArgs &a, const nsga3_problem &p, hipStream_t 
     xv.info = info;
     xv.sc = sc;
     xv.assoc_mode = a.assoc;
+    xv.niching_mode = a.niching;
     xv.mark = mk;
 #undef WS
     if (e == hipSuccess) e = run_select_stage(xv, stream);
@@ -442,8 +446,10 @@ nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt)
     c->opt.assoc = NSGA3_ASSOC_FP32;
     c->opt.autotune = 0;
     c->opt.max_workspace_bytes = 0;
+    c->opt.niching = NSGA3_NICHING_EXACT;
     if (opt) c->opt = *opt;
-    if (c->opt.assoc != NSGA3_ASSOC_FP32 && c->opt.assoc != NSGA3_ASSOC_BF16) {
+    if ((c->opt.assoc != NSGA3_ASSOC_FP32 && c->opt.assoc != NSGA3_ASSOC_BF16) ||
+        (c->opt.niching != NSGA3_NICHING_EXACT && c->opt.niching != NSGA3_NICHING_ONESHOT)) {
         delete c;
         return NSGA3_E_INVALID;
     }
@@ -562,6 +568,7 @@ nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t 
     a.ws = (char *)ctx->ws;
     a.cfg = ctx_cfg(ctx, M);
     a.assoc = (int)ctx->opt.assoc;
+    a.niching = (int)ctx->opt.niching;
     a.marks = ctx->profiling ? ctx : nullptr;
     a.last_fronts = ctx->last_fronts;
     const nsga3_problem p = {objs, N, M, refs, H, K, selected, rank, niche, dist,
@@ -998,7 +1005,9 @@ nsga3_status nsga3_plan_create(nsga3_ctx *ctx, const nsga3_problem *probs, int32
     if (!pl) return NSGA3_E_NOMEM;
     pl->device = ctx->device;
     const char *mode = getenv("NSGA3_PLAN_MODE");
-    if (!(mode && strcmp(mode, "graph") == 0)) {
+    // the engine implements the exact niching only: one-shot plans are graphs
+    // of single selections
+    if (!(mode && strcmp(mode, "graph") == 0) && ctx->opt.niching == NSGA3_NICHING_EXACT) {
         const nsga3_status st = plan_create_engine(ctx, probs, B, pl);
         if (st != NSGA3_OK) {
             plan_free(pl);
@@ -1071,6 +1080,7 @@ nsga3_status nsga3_plan_create(nsga3_ctx *ctx, const nsga3_problem *probs, int32
                 a.cfg.tail_block = true;       // cooperative launches cannot be captured
                 a.cfg.host_levels = levels;
                 a.assoc = (int)ctx->opt.assoc;
+                a.niching = (int)ctx->opt.niching;
                 a.marks = nullptr;
                 a.last_fronts = nullptr;
                 e = enqueue_select(a, probs[b], pl->streams[q]);

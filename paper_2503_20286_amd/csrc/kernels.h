@@ -19,6 +19,8 @@ size_t radix_sort_temp_bytes(int64_t n);
 void radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *k_alt, uint32_t *v_alt, int64_t n,
                       int nbits, uint32_t *temp, hipStream_t s, bool *in_alt);
 size_t compact_temp_bytes(int64_t n);
+// In-place exclusive scan of v[0..n) by one work-group; *total = the sum.
+void scan_inplace(uint32_t *v, int64_t n, uint32_t *total, hipStream_t s);
 // Writes at most `cap` indices; *total (device) receives the number of set flags.
 void compact_flags(const uint8_t *flag, int64_t n, int32_t *out, int64_t cap, uint32_t *temp,
                    uint32_t *total, hipStream_t s);
@@ -79,6 +81,7 @@ int peel_max_blocks_per_cu(int M);
 size_t split_state_entries(int64_t N);
 
 // ---- select.hip -----------------------------------------------------------
+size_t oneshot_temp_bytes(int64_t n);   // workspace temp needed by the one-shot niching
 struct SelectViews {
     const float *objs;
     int64_t N;
@@ -106,6 +109,7 @@ struct SelectViews {
     nsga3_info *info;            // caller's, may be null
     DevScalars *sc;
     int assoc_mode;
+    int niching_mode;            // NSGA3_NICHING_EXACT or NSGA3_NICHING_ONESHOT
     Marker mark;
 };
 

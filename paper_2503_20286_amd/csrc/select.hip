@@ -636,6 +636,122 @@ __global__ void k_finalize(nsga3_info *info, int64_t K, const DevScalars *__rest
     *info = v;
 }
 
+// ---------------------------------------------------------------------------
+// One-shot niche selection (Sec. IV-A.5; the niche-selection steps of
+// Alg. S.4 and the Update-Rank of Alg. S.6): instead of admitting last-front
+// members one at a time, every reference with no admitted member (rho_j = 0)
+// that has last-front members admits its closest one (distance, then index)
+// at once.  With |E| such picks and R places left, a shortfall R > |E| is
+// filled with the R - |E| lowest-index unpicked last-front members, a surplus
+// keeps the R lowest-index picks.  On the shuffled population the paper
+// takes as input, index order is a random order, so both fill rules are the
+// random choices the algorithm makes.
+// selflag values on entry: 1 admitted (rank < l), 0 otherwise; the picks are
+// marked 2 by k_oneshot_pick, and k_oneshot_apply leaves 0 / 1 everywhere.
+// ---------------------------------------------------------------------------
+constexpr int kOsTile = 2048;   // indices per count / apply work-group (8 x 256)
+
+// One wave per reference: the closest member of an empty niche's bucket.
+__global__ __launch_bounds__(256) void k_oneshot_pick(int H, const int32_t *__restrict__ rho,
+                                                      const int32_t *__restrict__ bstart,
+                                                      const double *__restrict__ bd,
+                                                      const int32_t *__restrict__ bi,
+                                                      uint8_t *__restrict__ selflag,
+                                                      const DevScalars *__restrict__ sc) {
+    if (sc->err) return;
+    const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (j >= H || rho[j] != 0) return;
+    const int32_t b0 = bstart[j], b1 = bstart[j + 1];
+    if (b1 <= b0) return;
+    double d = DBL_MAX;
+    int32_t i = INT32_MAX;
+    for (int32_t q = b0 + (int32_t)lane_id(); q < b1; q += kWave) {
+        const double dq = bd[q];
+        const int32_t iq = bi[q];
+        if (dq < d || (dq == d && iq < i)) { d = dq; i = iq; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double dq = __shfl_xor(d, o, 64);
+        const int32_t iq = __shfl_xor(i, o, 64);
+        if (dq < d || (dq == d && iq < i)) { d = dq; i = iq; }
+    }
+    if (lane_id() == 0) selflag[i] = 2;
+}
+
+// Per tile of kOsTile indices: number of picks (flag 2) and of unpicked
+// last-front members, in cnt[0 .. nb) and cnt[nbp .. nbp + nb).
+__global__ __launch_bounds__(256) void k_oneshot_count(int64_t N, const int32_t *__restrict__ rank,
+                                                       const uint8_t *__restrict__ selflag,
+                                                       uint32_t *__restrict__ cnt, int64_t nbp,
+                                                       const DevScalars *__restrict__ sc) {
+    __shared__ uint32_t red[2][4];
+    if (sc->err) return;
+    const int32_t l = sc->last_front;
+    const int64_t base = (int64_t)blockIdx.x * kOsTile;
+    uint32_t cp = 0, cq = 0;
+#pragma unroll
+    for (int it = 0; it < kOsTile / 256; ++it) {
+        const int64_t p = base + it * 256 + threadIdx.x;
+        if (p < N) {
+            const uint8_t f = selflag[p];
+            cp += f == 2 ? 1u : 0u;
+            cq += (f != 2 && rank[p] == l) ? 1u : 0u;
+        }
+    }
+    cp = wave_sum(cp);
+    cq = wave_sum(cq);
+    if (lane_id() == 0) {
+        red[0][threadIdx.x / kWave] = cp;
+        red[1][threadIdx.x / kWave] = cq;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cnt[blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        cnt[nbp + blockIdx.x] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+}
+
+// Final flags: a pick stays when R >= |E| or fewer than R picks precede it; an
+// unpicked last-front member is added when fewer than R - |E| of them precede
+// it.  off holds the exclusive tile prefixes of both counts (as cnt above);
+// totals[0] = |E|.
+__global__ __launch_bounds__(256) void k_oneshot_apply(int64_t N, const int32_t *__restrict__ rank,
+                                                       uint8_t *__restrict__ selflag,
+                                                       const uint32_t *__restrict__ off, int64_t nbp,
+                                                       const uint32_t *__restrict__ totals,
+                                                       const DevScalars *__restrict__ sc) {
+    __shared__ uint32_t lds[5];
+    if (sc->err) return;
+    const int32_t l = sc->last_front;
+    const int64_t R = sc->num_from_last;
+    const int64_t ne = totals[0];
+    const int64_t base = (int64_t)blockIdx.x * kOsTile;
+    int64_t op = off[blockIdx.x], oq = off[nbp + blockIdx.x];
+    for (int it = 0; it < kOsTile / 256; ++it) {
+        const int64_t p = base + it * 256 + threadIdx.x;
+        uint8_t f = 0;
+        bool member = false;
+        if (p < N) {
+            f = selflag[p];
+            member = rank[p] == l;
+        }
+        const uint32_t isP = f == 2 ? 1u : 0u;
+        const uint32_t isQ = (member && f != 2) ? 1u : 0u;
+        // picks in the low 16 bits, unpicked members in the high ones (<= 256 each)
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(isP | (isQ << 16), lds, &tot);
+        if (isP) selflag[p] = (R >= ne || op + (ex & 0xffffu) < R) ? 1 : 0;
+        if (isQ) selflag[p] = (R > ne && oq + (ex >> 16) < R - ne) ? 1 : 0;
+        op += tot & 0xffffu;
+        oq += tot >> 16;
+    }
+}
+
+size_t oneshot_temp_bytes(int64_t n) {
+    const int64_t nb = (n + kOsTile - 1) / kOsTile;
+    return (size_t)(2 * (nb + 64) + 64) * sizeof(uint32_t);
+}
+
 int normalize_partial_blocks(int64_t N) {
     int64_t nb = (N + kNormThreads - 1) / kNormThreads;
     if (nb > kNormBlocksMax) nb = kNormBlocksMax;
@@ -688,10 +804,24 @@ hipError_t run_select_stage(const SelectViews &v, hipStream_t s) {
                        v.bcursor, v.gstart, v.sc);
     hipLaunchKernelGGL(k_bucket_scatter, dim3(nbN), dim3(256), 0, s, N, v.H, v.rank, v.niche, v.dist64,
                        v.bcursor, v.bd, v.bi, v.sc);
-    // at most ceil(|F_l| / kRankMembers) + H groups, |F_l| <= N
-    const unsigned nbG = (unsigned)((N + kRankMembers - 1) / kRankMembers + v.H);
-    hipLaunchKernelGGL(k_bucket_rank, dim3(nbG), dim3(kRankGroup), 0, s, v.H, v.rho, v.bstart,
-                       v.gstart, v.bd, v.bi, v.selflag, v.sc);
+    if (v.niching_mode == NSGA3_NICHING_ONESHOT) {
+        hipLaunchKernelGGL(k_oneshot_pick, dim3((unsigned)((v.H + 3) / 4)), dim3(256), 0, s, v.H,
+                           v.rho, v.bstart, v.bd, v.bi, v.selflag, v.sc);
+        const int64_t nbo = (N + kOsTile - 1) / kOsTile;
+        const int64_t nbp = nbo + 64;
+        uint32_t *cnt = v.temp, *totals = v.temp + 2 * nbp;
+        hipLaunchKernelGGL(k_oneshot_count, dim3((unsigned)nbo), dim3(256), 0, s, N, v.rank,
+                           v.selflag, cnt, nbp, v.sc);
+        scan_inplace(cnt, nbo, totals, s);
+        scan_inplace(cnt + nbp, nbo, totals + 1, s);
+        hipLaunchKernelGGL(k_oneshot_apply, dim3((unsigned)nbo), dim3(256), 0, s, N, v.rank,
+                           v.selflag, cnt, nbp, totals, v.sc);
+    } else {
+        // at most ceil(|F_l| / kRankMembers) + H groups, |F_l| <= N
+        const unsigned nbG = (unsigned)((N + kRankMembers - 1) / kRankMembers + v.H);
+        hipLaunchKernelGGL(k_bucket_rank, dim3(nbG), dim3(kRankGroup), 0, s, v.H, v.rho, v.bstart,
+                           v.gstart, v.bd, v.bi, v.selflag, v.sc);
+    }
     compact_flags(v.selflag, N, v.selected, v.K, v.temp, &v.sc->n_selected, s);
     if (v.info) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, v.info, v.K, v.sc);
     v.mark();

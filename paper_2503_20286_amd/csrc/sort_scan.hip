@@ -184,6 +184,10 @@ __global__ __launch_bounds__(256) void k_cmp_write(const uint8_t *__restrict__ f
     }
 }
 
+void scan_inplace(uint32_t *v, int64_t n, uint32_t *total, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, v, n, total);
+}
+
 size_t compact_temp_bytes(int64_t n) {
     return (size_t)((n + kCmpTile - 1) / kCmpTile + 64) * sizeof(uint32_t);
 }

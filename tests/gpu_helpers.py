@@ -50,12 +50,16 @@ def line_distance64(objs, z, a, refs, ref_idx):
     return np.sqrt(q)
 
 
-def compare_full(objs, refs, K, g, with_counts=True, s=None):
+def compare_full(objs, refs, K, g, with_counts=True, s=None, niching="exact"):
     """Element-by-element comparison with the oracle's whole selection ``s``
-    (computed here when not given).  Returns a dict of mismatch counts (all
-    must be zero) and the number of near-tie points."""
+    (computed here when not given) under the niching rule ``niching``
+    ("exact": the loop of Alg. S.1, "oneshot": the one-shot form).  Returns a
+    dict of mismatch counts (all must be zero) and the number of near-tie
+    points."""
     if s is None:
-        s = oracle.select(objs, refs, K, with_counts=with_counts)
+        s = oracle.select(objs, refs, K, with_counts=with_counts, niching=niching)
+    pick = oracle.niching if niching == "exact" else (
+        lambda *a: oracle.niching_oneshot(*a)[0])
     rep = {}
     rep["rank"] = int(np.sum(g["rank"] != s.rank))
     if with_counts:
@@ -88,7 +92,7 @@ def compare_full(objs, refs, K, g, with_counts=True, s=None):
         moved = tie & (g["niche"] != niche)
         if np.any(moved):
             d64[moved] = line_distance64(objs[moved], nz.z, nz.a, refs, g["niche"][moved])
-        chosen = oracle.niching(g["rank"], g["niche"], d64, l, refs.shape[0], s.num_from_last, rho)
+        chosen = pick(g["rank"], g["niche"], d64, l, refs.shape[0], s.num_from_last, rho)
         want = np.nonzero((g["rank"] < l) | chosen)[0]
         rep["selected"] = _sel_mismatch(g["selected"], want)
     rep["near_ties"] = int(np.sum(tie))

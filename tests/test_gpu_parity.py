@@ -265,6 +265,86 @@ def test_bf16_objective_counts(M):
     _zero(compare_full(F, R, 600, g))
 
 
+# ---------------------------------------------------------------------------
+# One-shot niche selection (Sec. IV-A.5, Alg. S.4, Alg. S.6) against the
+# oracle's one-shot form.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,N,assoc", [("small", None, "fp32"), ("ties", 3000, "fp32"),
+                                          ("large", 5000, "fp32"), ("many", 4000, "bf16"),
+                                          ("ties", None, "fp32")])
+def test_oneshot_niching_parity(name, N, assoc):
+    import paper_2503_20286_amd as nsga3
+    w = workloads.make(name, N=N)
+    mode = nsga3.ASSOC_BF16 if assoc == "bf16" else nsga3.ASSOC_FP32
+    print(f"oneshot {name} N={w.N} {assoc}", flush=True)
+    for K in sorted({1, w.K, w.N}):
+        g = gpu_select(w.objs, w.refs, K, assoc=mode, niching=nsga3.NICHING_ONESHOT)
+        _zero(compare_full(w.objs, w.refs, K, g, niching="oneshot"))
+
+
+def test_oneshot_surplus_shortfall_and_exact_fill():
+    """K chosen so that the last front's shortfall R is below, equal to and
+    above the number of empty-niche picks |E| (last front 0 and 1; 496
+    references, so that many niches are empty)."""
+    import paper_2503_20286_amd as nsga3
+    w = workloads.make("ties", N=4000, seed=12)
+    refs = workloads.das_dennis(3, 30).astype(np.float32)
+    r, _ = oracle.ranks(w.objs)
+    sizes = np.bincount(r)
+    for l in (0, 1):
+        nb = int(sizes[:l].sum())
+        s = oracle.select(w.objs, refs, nb + 1, with_counts=False)
+        assert s.last_front == l
+        rho = oracle.niche_count(s.rank, s.niche, l, refs.shape[0])
+        _, ne = oracle.niching_oneshot(s.rank, s.niche, s.dist, l, refs.shape[0], 1, rho)
+        assert ne >= 3
+        for R in (1, ne - 1, ne, ne + 1, int(sizes[l])):
+            K = nb + R
+            print(f"oneshot l={l} |E|={ne} R={R}", flush=True)
+            g = gpu_select(w.objs, refs, K, niching=nsga3.NICHING_ONESHOT)
+            assert g["info"].last_front == l and g["info"].num_from_last == R
+            _zero(compare_full(w.objs, refs, K, g, niching="oneshot"))
+
+
+def test_oneshot_full_size_every_point():
+    import paper_2503_20286_amd as nsga3
+    w, s = _oracle_full("large")
+    l = s.last_front
+    rho = oracle.niche_count(s.rank, s.niche, l, w.H)
+    chosen, _ = oracle.niching_oneshot(s.rank, s.niche, s.dist, l, w.H, s.num_from_last, rho)
+    want = np.nonzero((s.rank < l) | chosen)[0]
+    g = gpu_select(w.objs, w.refs, w.K, niching=nsga3.NICHING_ONESHOT)
+    assert np.array_equal(g["rank"], s.rank)
+    assert np.array_equal(g["niche"], s.niche)
+    assert np.array_equal(g["selected"], want)
+
+
+def test_oneshot_plan_matches_single_calls():
+    """Batched plans of a one-shot context run as graphs of single calls."""
+    import torch
+    import paper_2503_20286_amd as nsga3
+    ws = workloads.make_batch(10, n_lo=50, n_hi=4000, base_seed=8800)
+    probs = [(torch.from_numpy(w.objs).cuda(), torch.from_numpy(w.refs).cuda(), w.K) for w in ws]
+    ctx = nsga3.Context(0, niching=nsga3.NICHING_ONESHOT)
+    plan = nsga3.Plan(probs, ctx=ctx)
+    for _ in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        for b, (o, r, K) in enumerate(probs):
+            single = nsga3.select(o, r, K, ctx=ctx)
+            torch.cuda.synchronize()
+            assert torch.equal(plan.results[b].selected, single.selected), b
+    for b in (0, 4, 9):
+        w = ws[b]
+        res = plan.results[b]
+        g = {k: getattr(res, k).cpu().numpy() for k in ("selected", "rank", "niche", "dist",
+                                                        "dom_in", "dom_out")}
+        g["info"] = res.info()
+        _zero(compare_full(w.objs, w.refs, w.K, g, niching="oneshot"))
+    plan.close()
+    ctx.close()
+
+
 @pytest.mark.parametrize("name,N", [("ties", 3000), ("large", 5000), ("many", 3000)])
 def test_pairwise_compare_path_parity(name, N, monkeypatch):
     """The pairwise-compare dominance kernels (kept beside the block-bitset
