@@ -56,6 +56,7 @@ struct nsga3_ctx {
     int phase_a_bpc;
     bool bitsets;
     bool tail_block;
+    int out_mode;                   // NSGA3_SEPARATE_OUT: LaunchCfg::out_mode
     int fixed_levels;               // > 0: always enqueue this many peeling levels
     volatile int32_t *last_fronts;  // pinned: front count of the latest call
     std::vector<hipEvent_t> ev_pool;   // NSGA3_NUM_PHASES + 1 events per recorded call
@@ -214,6 +215,7 @@ LaunchCfg ctx_cfg(const nsga3_ctx *ctx, int M) {
     cfg.phase_a_blocks_per_cu = ctx->phase_a_bpc;
     cfg.bitsets = ctx->bitsets;
     cfg.tail_block = ctx->tail_block;
+    cfg.out_mode = ctx->out_mode;
     // enqueue one more level than the previous call needed (its front count
     // arrives asynchronously in pinned memory; a stale value only shifts work
     // between the enqueued levels and the tail)
@@ -305,6 +307,7 @@ hipError_t enqueue_select(const EnqArgs &a, const nsga3_problem &p, hipStream_t 
     sv.sc = sc;
     sv.bar = WS(GridBar, bar);
     sv.mark = mk;
+    sv.out_mode = a.cfg.out_mode;
     const LaunchCfg &cfg = a.cfg;
     if (e == hipSuccess) e = run_sort_stage(sv, cfg, stream);
     if (e == hipSuccess && a.last_fronts)
@@ -488,6 +491,11 @@ nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt)
     // cooperative grid (the form captured graphs use; same results)
     c->tail_block = false;
     if (const char *e = getenv("NSGA3_TAIL_BLOCK")) c->tail_block = atoi(e) != 0;
+    // NSGA3_SEPARATE_OUT=1 / 0: out-degrees always by their own backward pass
+    // / always from the in-degree pass's probes (same results); unset: chosen
+    // by the objective count
+    c->out_mode = -1;
+    if (const char *e = getenv("NSGA3_SEPARATE_OUT")) c->out_mode = atoi(e) != 0 ? 1 : 0;
     if (const char *e = getenv("NSGA3_HOST_LEVELS")) {
         const int v = atoi(e);
         if (v >= 1 && v <= kMaxHostLevels) c->fixed_levels = v;
@@ -698,7 +706,7 @@ static nsga3_status tune_group(nsga3_ctx *ctx, const std::vector<nsga3::EInst> &
             if (e == hipSuccess) e = engine_launch(M, d_inst, d_state, 0, nb, d_glob, nullptr, kSDom, grid, s);
             if (e == hipSuccess)
                 e = engine_bitdom_launch(M, d_inst, d_state, d_map, (int64_t)nmap, d_map + nmap,
-                                         (int64_t)cmap.size(), s);
+                                         (int64_t)cmap.size(), ctx->out_mode, s);
             if (e == hipSuccess) e = engine_resume(d_inst, d_state, 0, nb, d_glob + 1, s);
             if (e == hipSuccess) e = engine_launch(M, d_inst, d_state, 0, nb, d_glob + 1, nullptr, kSDone, grid, s);
             if (e == hipSuccess) e = hipEventRecord(e1, s);
@@ -905,7 +913,7 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
         if (pl->bitdom)
             return engine_bitdom_launch(M, pl->d_inst, pl->d_state, pl->d_bmap + boff[c],
                                         boff[c + 1] - boff[c], pl->d_cmap + coff[c],
-                                        coff[c + 1] - coff[c], st);
+                                        coff[c + 1] - coff[c], ctx->out_mode, st);
         return engine_dom_launch(M, pl->d_inst, pl->d_state, pl->d_map + map_off[c],
                                  map_off[c + 1] - map_off[c], st);
     };

@@ -210,11 +210,16 @@ __device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__re
 }
 
 // Forward: for each of the wave's kTJ x 64 points j (keys kj, run starts run),
-// add the number of members of the staged blocks that dominate j.
-template <int M, int TJ = kTJ>
+// add the number of members of the staged blocks that dominate j.  With kOut,
+// every dominating member also gains one in its LDS counter oc[b * 64 + bit]
+// (block b of the staged chunk, bit = its index in the block): the same
+// probes then give the out-degrees of the staged members, since every
+// dominance pair (i before j's run) is probed exactly once.
+template <int M, int TJ = kTJ, bool kOut = false>
 __device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32_t run_lo,
                                            int32_t run_hi, const uint32_t (&kj)[TJ][M],
-                                           const int32_t (&run)[TJ], int32_t (&cnt)[TJ]) {
+                                           const int32_t (&run)[TJ], int32_t (&cnt)[TJ],
+                                           uint32_t *oc = nullptr) {
     constexpr int TS = blk_stride(M);
     for (int32_t b = 0; b < nb; ++b) {
         const uint32_t *T = lt + b * TS;
@@ -245,6 +250,14 @@ __device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32
 #pragma unroll
             for (int k = 0; k < M; ++k) m &= prefix_mask(T + blk_pm_off(M, k), c[t * M + k]);
             cnt[t] += __popcll(m);
+            if constexpr (kOut) {
+                uint32_t *ob = oc + b * kBlk;
+                while (m) {
+                    const uint32_t bit = (uint32_t)__builtin_ctzll(m);
+                    __hip_atomic_fetch_add(ob + bit, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    m &= m - 1ull;
+                }
+            }
         }
     }
 }

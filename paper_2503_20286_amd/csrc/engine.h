@@ -190,9 +190,10 @@ hipError_t engine_resume(const EInst *inst, EState *st, int32_t b0, int32_t nb, 
 // Block-bitset dominance counts of every parked instance (bitdom.hip): block
 // tables (bmap[q] = (instance, block), nb_build entries), then in-degrees and
 // out-degrees (cmap[q] = (instance, work-group), nb_count entries).
+// out_mode as LaunchCfg::out_mode.
 hipError_t engine_bitdom_launch(int M, const EInst *inst, const EState *st, const int2 *bmap,
                                 int64_t nb_build, const int2 *cmap, int64_t nb_count,
-                                hipStream_t s);
+                                int out_mode, hipStream_t s);
 // Block tables and count work-groups of one instance for the launch above.
 void engine_bitdom_items(int64_t N, int M, int64_t *n_build, int64_t *n_count);
 

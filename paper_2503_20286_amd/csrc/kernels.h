@@ -50,6 +50,7 @@ struct SortViews {
     size_t lb_stride;
     uint32_t *blkcnt;            // [2 * max grid] per-block counts
     int32_t *rank, *dom_in, *dom_out;  // outputs in original order (dom_* may be null)
+    int out_mode = -1;                 // as LaunchCfg::out_mode
     DevScalars *sc;
     GridBar *bar;                // grid-barrier state (zeroed per call)
     Marker mark;
@@ -64,7 +65,13 @@ struct LaunchCfg {
     int host_levels;            // peeling levels enqueued as ordinary launches
     bool bitsets;               // block-bitset pair kernels (else pairwise compares)
     bool tail_block;            // single-workgroup peeling tail (graph capture)
+    int out_mode = -1;          // out-degrees: -1 by objective count, 0 from the in-degree
+                                // pass, 1 by their own backward pass
 };
+
+// Whether out-degrees come from the in-degree pass's probes (each dominating
+// member counted in LDS) rather than a backward pass of their own.
+bool fused_out_counts(int M, int out_mode);
 
 hipError_t run_sort_stage(const SortViews &v, const LaunchCfg &cfg, hipStream_t s);
 

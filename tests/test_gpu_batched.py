@@ -267,3 +267,22 @@ def test_engine_pairwise_counts_match(monkeypatch):
             assert np.array_equal(a[b][k], h[k]), (b, k)
     plan.close()
     plan2.close()
+
+
+@pytest.mark.parametrize("separate", ["0", "1"])
+def test_engine_out_degree_forms_match(separate, monkeypatch):
+    """Batched counts with out-degrees from the in-degree probes or from the
+    backward pass, for every objective count, equal single calls."""
+    import torch
+    import paper_2503_20286_amd as nsga3
+    ws = workloads.make_batch(9, n_lo=50, n_hi=6000, base_seed=8400)
+    probs = _dev(ws)
+    monkeypatch.setenv("NSGA3_SEPARATE_OUT", separate)
+    ctx = nsga3.Context(0)
+    plan = nsga3.Plan(probs, ctx=ctx)
+    plan.launch()
+    torch.cuda.synchronize()
+    monkeypatch.delenv("NSGA3_SEPARATE_OUT")
+    _check_against_single(plan, probs, ("out", separate))
+    plan.close()
+    ctx.close()

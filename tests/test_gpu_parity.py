@@ -359,6 +359,28 @@ def test_pairwise_compare_path_parity(name, N, monkeypatch):
     ctx.close()
 
 
+@pytest.mark.parametrize("separate", ["0", "1"])
+def test_out_degree_forms_parity(separate, monkeypatch):
+    """Out-degrees counted inside the in-degree probes (NSGA3_SEPARATE_OUT=0)
+    and by their own backward pass (=1) give the oracle's counts for every
+    objective count (the default picks one form by M)."""
+    import paper_2503_20286_amd as nsga3
+    monkeypatch.setenv("NSGA3_SEPARATE_OUT", separate)
+    ctx = nsga3.Context(0)
+    monkeypatch.delenv("NSGA3_SEPARATE_OUT")
+    rng = np.random.default_rng(40)
+    cases = [workloads.make("ties", N=3000), workloads.make("large", N=5000),
+             workloads.make("many", N=3000)]
+    for w in cases:
+        g = gpu_select(w.objs, w.refs, w.K, ctx=ctx)
+        _zero(compare_full(w.objs, w.refs, w.K, g))
+    F = rng.integers(0, 50, size=(2500, 2)).astype(np.float32)   # dense two-objective dominance
+    R = workloads.das_dennis(2, 30).astype(np.float32)
+    g = gpu_select(F, R, 1200, ctx=ctx)
+    _zero(compare_full(F, R, 1200, g))
+    ctx.close()
+
+
 @pytest.mark.parametrize("tail_block,levels", [(True, 2), (False, 1), (True, 5)])
 def test_peeling_tails(tail_block, levels, monkeypatch):
     """Levels beyond the enqueued ones are finished by the cooperative tail or
