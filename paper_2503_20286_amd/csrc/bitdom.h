@@ -94,6 +94,56 @@ __device__ __forceinline__ void count_many64(const uint32_t *const (&S)[R], cons
     }
 }
 
+// LDS byte addresses.  A generic pointer to LDS holds the LDS offset in its
+// low 32 bits, so the searches below keep one 32-bit address per search and
+// every read takes its step as the instruction's immediate offset.
+typedef __attribute__((address_space(3))) const uint32_t lds_cu32;
+__device__ __forceinline__ uint32_t lds_addr(const uint32_t *p) { return (uint32_t)(uintptr_t)p; }
+__device__ __forceinline__ uint32_t lds_ld(uint32_t a) { return *(lds_cu32 *)(uintptr_t)a; }
+
+// For R independent probes of block table T: the prefix mask of objective
+// k[r] at "number of member keys <= x[r]" (kLe) or "< x[r]".  Each search is
+// seven halving steps over the 64 sorted keys (32, 16, 8, 4, 2, 1, then 1
+// more, which separates 63 from 64) on a running LDS address, all R reads of
+// a step issued before any compare; a step is one read, one compare, one
+// select and one add.  The mask entry sits at a fixed distance from the key
+// the search ends on, so its two reads need no address arithmetic.
+template <int M, int R, bool kLe>
+__device__ __forceinline__ void masks_many64(const uint32_t *T, const int (&k)[R],
+                                             const uint32_t (&x)[R], uint64_t (&mask)[R]) {
+    const uint32_t base = lds_addr(T);
+    uint32_t a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t kb = base + 4u * (uint32_t)blk_key_off(k[r]);
+        const uint32_t v = lds_ld(kb + 4u * 31u);
+        a[r] = kb + ((kLe ? v <= x[r] : v < x[r]) ? 128u : 0u);
+    }
+#pragma unroll
+    for (int step = 16; step >= 1; step >>= 1) {
+        uint32_t v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = lds_ld(a[r] + 4u * (uint32_t)(step - 1));
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] += (kLe ? v[r] <= x[r] : v[r] < x[r]) ? 4u * step : 0u;
+    }
+    {
+        uint32_t v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = lds_ld(a[r]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] += (kLe ? v[r] <= x[r] : v[r] < x[r]) ? 4u : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        // entry c of objective k[r]'s masks: c = (a - key base) / 4
+        const uint32_t d = 4u * (uint32_t)(blk_pm_off(M, k[r]) - blk_key_off(k[r]));
+        const uint32_t lo = lds_ld(a[r] + d);
+        const uint32_t hi = lds_ld(a[r] + d + 4u * 65u);
+        mask[r] = (uint64_t)lo | ((uint64_t)hi << 32);
+    }
+}
+
 __device__ __forceinline__ uint64_t low_bits(uint32_t c) {
     return c >= 64u ? ~0ull : ((1ull << c) - 1ull);
 }
@@ -228,16 +278,17 @@ __device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32
         if (bmin >= run_hi) break;  // later blocks start later still
         const bool full = bmax < run_lo;
         // the TJ x M key searches in lockstep
-        const uint32_t *S[TJ * M];
-        uint32_t x[TJ * M], c[TJ * M];
+        int ko[TJ * M];
+        uint32_t x[TJ * M];
+        uint64_t pm[TJ * M];
 #pragma unroll
         for (int t = 0; t < TJ; ++t)
 #pragma unroll
             for (int k = 0; k < M; ++k) {
-                S[t * M + k] = T + blk_key_off(k);
+                ko[t * M + k] = k;
                 x[t * M + k] = kj[t][k];
             }
-        count_many64<TJ * M, true>(S, x, c);
+        masks_many64<M, TJ * M, true>(T, ko, x, pm);
 #pragma unroll
         for (int t = 0; t < TJ; ++t) {
             uint64_t m = ~0ull;
@@ -248,7 +299,7 @@ __device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32
                                                 run[t]));
             }
 #pragma unroll
-            for (int k = 0; k < M; ++k) m &= prefix_mask(T + blk_pm_off(M, k), c[t * M + k]);
+            for (int k = 0; k < M; ++k) m &= pm[t * M + k];
             cnt[t] += __popcll(m);
             if constexpr (kOut) {
                 uint32_t *ob = oc + b * kBlk;

@@ -212,16 +212,17 @@ __device__ __forceinline__ void bwd_blocks(const uint32_t *lt, int32_t nb, int32
         if (bmax < rend_lo) continue;  // the whole block precedes every run end
         const uint64_t members = low_bits(T[2]);
         const bool full = bmin >= rend_hi;
-        const uint32_t *S[kTJ * M];
-        uint32_t x[kTJ * M], c[kTJ * M];
+        int ko[kTJ * M];
+        uint32_t x[kTJ * M];
+        uint64_t pm[kTJ * M];
 #pragma unroll
         for (int t = 0; t < kTJ; ++t)
 #pragma unroll
             for (int k = 0; k < M; ++k) {
-                S[t * M + k] = T + blk_key_off(k);
+                ko[t * M + k] = k;
                 x[t * M + k] = ki[t][k];
             }
-        count_many64<kTJ * M, false>(S, x, c);
+        masks_many64<M, kTJ * M, false>(T, ko, x, pm);
 #pragma unroll
         for (int t = 0; t < kTJ; ++t) {
             uint64_t m = members;
@@ -232,7 +233,7 @@ __device__ __forceinline__ void bwd_blocks(const uint32_t *lt, int32_t nb, int32
                                                   rend[t]));
             }
 #pragma unroll
-            for (int k = 0; k < M; ++k) m &= ~prefix_mask(T + blk_pm_off(M, k), c[t * M + k]);
+            for (int k = 0; k < M; ++k) m &= ~pm[t * M + k];
             cnt[t] += __popcll(m);
         }
     }
