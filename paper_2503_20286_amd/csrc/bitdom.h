@@ -17,39 +17,21 @@ constexpr int kBlk = 64;  // members per block
 // Per-block table layout, in dwords:
 //   [0..3]              header: min position, max position, member count, 0
 //   [4..67]             member positions (ascending; padding 0x7fffffff)
-//   [68 .. 68+64M)      per objective: the 64 member keys, sorted (padding 0xffffffff)
-//   [68+64M .. +130M)   per objective: 65 prefix masks (entry c = first c members), as
+//   [68 .. 68+32M)      per objective: the 32 smallest member keys, sorted
+//   [69+32M .. 69+64M)  per objective: the 32 largest member keys, sorted (padding
+//                       0xffffffff); one spare dword before them puts the two halves of an
+//                       objective one LDS bank apart
+//   [69+64M .. +130M)   per objective: 65 prefix masks (entry c = first c members), as
 //                       65 low dwords then 65 high dwords (a lane reading entry c hits
 //                       bank c, so lanes with different counts do not conflict)
 __host__ __device__ constexpr int blk_pos_off() { return 4; }
-__host__ __device__ constexpr int blk_key_off(int k) { return 68 + 64 * k; }
-__host__ __device__ constexpr int blk_pm_off(int M, int k) { return 68 + 64 * M + 130 * k; }
-__host__ __device__ constexpr int blk_stride(int M) { return ((68 + 194 * M) + 3) / 4 * 4; }
-
-// Number of the 64 sorted keys S that are <= x, in [0, 64] (S padded with
-// 0xffffffff, and x is always below the padding).
-__device__ __forceinline__ uint32_t count_le64(const uint32_t *S, uint32_t x) {
-    uint32_t c = (S[31] <= x) ? 32u : 0u;
-    c += (S[c + 15] <= x) ? 16u : 0u;
-    c += (S[c + 7] <= x) ? 8u : 0u;
-    c += (S[c + 3] <= x) ? 4u : 0u;
-    c += (S[c + 1] <= x) ? 2u : 0u;
-    c += (S[c] <= x) ? 1u : 0u;
-    c += (c == 63u && S[63] <= x) ? 1u : 0u;  // six halvings reach 63 at most
-    return c;
+__host__ __device__ constexpr int blk_key_lo(int k) { return 68 + 32 * k; }
+__host__ __device__ constexpr int blk_key_hi(int M, int k) { return 69 + 32 * M + 32 * k; }
+__host__ __device__ constexpr int blk_key_slot(int M, int k, int r) {
+    return r < 32 ? blk_key_lo(k) + r : blk_key_hi(M, k) + (r - 32);
 }
-
-// Number of the 64 sorted keys S that are < x.
-__device__ __forceinline__ uint32_t count_lt64(const uint32_t *S, uint32_t x) {
-    uint32_t c = (S[31] < x) ? 32u : 0u;
-    c += (S[c + 15] < x) ? 16u : 0u;
-    c += (S[c + 7] < x) ? 8u : 0u;
-    c += (S[c + 3] < x) ? 4u : 0u;
-    c += (S[c + 1] < x) ? 2u : 0u;
-    c += (S[c] < x) ? 1u : 0u;
-    c += (c == 63u && S[63] < x) ? 1u : 0u;
-    return c;
-}
+__host__ __device__ constexpr int blk_pm_off(int M, int k) { return 69 + 64 * M + 130 * k; }
+__host__ __device__ constexpr int blk_stride(int M) { return ((69 + 194 * M) + 3) / 4 * 4; }
 
 // Number of member positions (sorted, padded with 0x7fffffff) below bound.
 __device__ __forceinline__ uint32_t count_pos_lt64(const int32_t *P, int32_t bound) {
@@ -63,61 +45,35 @@ __device__ __forceinline__ uint32_t count_pos_lt64(const int32_t *P, int32_t bou
     return c;
 }
 
-// Prefix mask entry c of objective table P (low dwords, then high dwords).
-__device__ __forceinline__ uint64_t prefix_mask(const uint32_t *P, uint32_t c) {
-    return (uint64_t)P[c] | ((uint64_t)P[65 + c] << 32);
-}
-
-// Lockstep form of count_le64 / count_lt64 for R independent searches (S[r]
-// sorted 64-key arrays, x[r] the probes): every halving step issues all R
-// reads before any compare, so the LDS latency is paid once per step.
-// The search keeps a running pointer into S, so a step is one read (the
-// step offset is an immediate), one compare, one select and one add.
-template <int R, bool kLe>
-__device__ __forceinline__ void count_many64(const uint32_t *const (&S)[R], const uint32_t (&x)[R],
-                                             uint32_t (&c)[R]) {
-    const uint32_t *p[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) p[r] = S[r] + ((kLe ? S[r][31] <= x[r] : S[r][31] < x[r]) ? 32 : 0);
-#pragma unroll
-    for (int step = 16; step >= 1; step >>= 1) {
-        uint32_t v[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = p[r][step - 1];
-#pragma unroll
-        for (int r = 0; r < R; ++r) p[r] += (kLe ? v[r] <= x[r] : v[r] < x[r]) ? step : 0;
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        c[r] = (uint32_t)(p[r] - S[r]);
-        c[r] += (c[r] == 63u && (kLe ? S[r][63] <= x[r] : S[r][63] < x[r])) ? 1u : 0u;
-    }
-}
-
 // LDS byte addresses.  A generic pointer to LDS holds the LDS offset in its
-// low 32 bits, so the searches below keep one 32-bit address per search and
-// every read takes its step as the instruction's immediate offset.
+// low 32 bits, so the searches below work on 32-bit LDS addresses.
 typedef __attribute__((address_space(3))) const uint32_t lds_cu32;
 __device__ __forceinline__ uint32_t lds_addr(const uint32_t *p) { return (uint32_t)(uintptr_t)p; }
 __device__ __forceinline__ uint32_t lds_ld(uint32_t a) { return *(lds_cu32 *)(uintptr_t)a; }
 
 // For R independent probes of block table T: the prefix mask of objective
-// k[r] at "number of member keys <= x[r]" (kLe) or "< x[r]".  Each search is
-// seven halving steps over the 64 sorted keys (32, 16, 8, 4, 2, 1, then 1
-// more, which separates 63 from 64) on a running LDS address, all R reads of
-// a step issued before any compare; a step is one read, one compare, one
-// select and one add.  The mask entry sits at a fixed distance from the key
-// the search ends on, so its two reads need no address arithmetic.
+// k[r] at "number of member keys <= x[r]" (kLe) or "< x[r]".  Each search
+// keeps a running LDS address: the first step picks the lower or the upper
+// half of the keys (32 each), five halving steps and a last one-key step
+// follow inside that half, each one read (the step is the instruction's
+// immediate offset), one compare, one select and one add; all R reads of a
+// step are issued before any compare.  The two halves sit one bank apart, so
+// lanes searching the same block in different halves do not conflict.  Mask
+// entry c lies at a fixed distance from the key the search ends on (minus the
+// spare dword in the upper half).
 template <int M, int R, bool kLe>
 __device__ __forceinline__ void masks_many64(const uint32_t *T, const int (&k)[R],
                                              const uint32_t (&x)[R], uint64_t (&mask)[R]) {
     const uint32_t base = lds_addr(T);
-    uint32_t a[R];
+    uint32_t a[R], up[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const uint32_t kb = base + 4u * (uint32_t)blk_key_off(k[r]);
-        const uint32_t v = lds_ld(kb + 4u * 31u);
-        a[r] = kb + ((kLe ? v <= x[r] : v < x[r]) ? 128u : 0u);
+        const uint32_t lo = base + 4u * (uint32_t)blk_key_lo(k[r]);
+        const uint32_t v = lds_ld(lo + 4u * 31u);
+        // upper half: address of key 32 (blk_key_hi) instead of key 0
+        up[r] = (kLe ? v <= x[r] : v < x[r]) ? 4u * (uint32_t)(blk_key_hi(M, k[r]) - blk_key_lo(k[r]))
+                                             : 0u;
+        a[r] = lo + up[r];
     }
 #pragma unroll
     for (int step = 16; step >= 1; step >>= 1) {
@@ -136,10 +92,11 @@ __device__ __forceinline__ void masks_many64(const uint32_t *T, const int (&k)[R
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        // entry c of objective k[r]'s masks: c = (a - key base) / 4
-        const uint32_t d = 4u * (uint32_t)(blk_pm_off(M, k[r]) - blk_key_off(k[r]));
-        const uint32_t lo = lds_ld(a[r] + d);
-        const uint32_t hi = lds_ld(a[r] + d + 4u * 65u);
+        // c = (a - lower base) / 4, less the upper half's shift (which is 32 keys + 1)
+        const uint32_t d = 4u * (uint32_t)(blk_pm_off(M, k[r]) - blk_key_lo(k[r]));
+        const uint32_t e = a[r] + d - up[r] + (up[r] ? 128u : 0u);
+        const uint32_t lo = lds_ld(e);
+        const uint32_t hi = lds_ld(e + 4u * 65u);
         mask[r] = (uint64_t)lo | ((uint64_t)hi << 32);
     }
 }
@@ -228,7 +185,7 @@ __device__ __forceinline__ void build_block(const uint32_t *__restrict__ rec, in
             const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)key, m);
             rank += (o < key || (o == key && m < l)) ? 1u : 0u;
         }
-        T[blk_key_off(k) + rank] = key;
+        T[blk_key_slot(M, k, (int)rank)] = key;
         inv[rank] = l;
         block_sync<kWaveSync>();
         const int mem = inv[l];
