@@ -17,21 +17,24 @@ constexpr int kBlk = 64;  // members per block
 // Per-block table layout, in dwords:
 //   [0..3]              header: min position, max position, member count, 0
 //   [4..67]             member positions (ascending; padding 0x7fffffff)
-//   [68 .. 68+32M)      per objective: the 32 smallest member keys, sorted
-//   [69+32M .. 69+64M)  per objective: the 32 largest member keys, sorted (padding
-//                       0xffffffff); one spare dword before them puts the two halves of an
-//                       objective one LDS bank apart
-//   [69+64M .. +130M)   per objective: 65 prefix masks (entry c = first c members), as
-//                       65 low dwords then 65 high dwords (a lane reading entry c hits
-//                       bank c, so lanes with different counts do not conflict)
+//   [68 + 195k ..)      per objective k, two regions 97 dwords apart (97 = 1 mod 32:
+//                       one LDS bank apart), for the member-key ranks c < 32 and c >= 32:
+//                         lower  [keys 0..31 | mask lows c = 0..31 | 1 spare | mask highs 0..31]
+//                         upper  [keys 32..63 | mask lows c = 32..64 | mask highs 32..64]
+//                       keys sorted (padding 0xffffffff); mask entry c is the set of the c
+//                       members with the smallest keys, its low dword 32 and its high dword
+//                       65 dwords after key slot c (key slot 64 being one past key 63)
 __host__ __device__ constexpr int blk_pos_off() { return 4; }
-__host__ __device__ constexpr int blk_key_lo(int k) { return 68 + 32 * k; }
-__host__ __device__ constexpr int blk_key_hi(int M, int k) { return 69 + 32 * M + 32 * k; }
-__host__ __device__ constexpr int blk_key_slot(int M, int k, int r) {
-    return r < 32 ? blk_key_lo(k) + r : blk_key_hi(M, k) + (r - 32);
+constexpr int kBlkUpper = 97;   // upper region offset in dwords
+__host__ __device__ constexpr int blk_obj_off(int k) { return 68 + 195 * k; }
+__host__ __device__ constexpr int blk_key_slot(int k, int c) {
+    return c < 32 ? blk_obj_off(k) + c : blk_obj_off(k) + kBlkUpper + (c - 32);
 }
-__host__ __device__ constexpr int blk_pm_off(int M, int k) { return 69 + 64 * M + 130 * k; }
-__host__ __device__ constexpr int blk_stride(int M) { return ((69 + 194 * M) + 3) / 4 * 4; }
+__host__ __device__ constexpr int blk_mask_lo(int k, int c) { return blk_key_slot(k, c) + 32; }
+__host__ __device__ constexpr int blk_mask_hi(int k, int c) { return blk_key_slot(k, c) + 65; }
+// (blk_stride(M), the table size in dwords, is in common.h: the batched
+// engine's workspace layout needs it too.)
+static_assert(blk_stride(16) >= blk_obj_off(16), "table stride covers every objective");
 
 // Number of member positions (sorted, padded with 0x7fffffff) below bound.
 __device__ __forceinline__ uint32_t count_pos_lt64(const int32_t *P, int32_t bound) {
@@ -54,26 +57,22 @@ __device__ __forceinline__ uint32_t lds_ld(uint32_t a) { return *(lds_cu32 *)(ui
 // For R independent probes of block table T: the prefix mask of objective
 // k[r] at "number of member keys <= x[r]" (kLe) or "< x[r]".  Each search
 // keeps a running LDS address: the first step picks the lower or the upper
-// half of the keys (32 each), five halving steps and a last one-key step
-// follow inside that half, each one read (the step is the instruction's
-// immediate offset), one compare, one select and one add; all R reads of a
-// step are issued before any compare.  The two halves sit one bank apart, so
-// lanes searching the same block in different halves do not conflict.  Mask
-// entry c lies at a fixed distance from the key the search ends on (minus the
-// spare dword in the upper half).
+// region (32 keys each), five halving steps and a last one-key step follow
+// inside that region, each one read (the step is the instruction's immediate
+// offset), one compare, one select and one add; all R reads of a step are
+// issued before any compare.  The regions sit one bank apart, so lanes that
+// search the same block in different halves do not conflict.  The search ends
+// on key slot c, and mask entry c lies at fixed distances from it.
 template <int M, int R, bool kLe>
 __device__ __forceinline__ void masks_many64(const uint32_t *T, const int (&k)[R],
                                              const uint32_t (&x)[R], uint64_t (&mask)[R]) {
     const uint32_t base = lds_addr(T);
-    uint32_t a[R], up[R];
+    uint32_t a[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const uint32_t lo = base + 4u * (uint32_t)blk_key_lo(k[r]);
+        const uint32_t lo = base + 4u * (uint32_t)blk_obj_off(k[r]);
         const uint32_t v = lds_ld(lo + 4u * 31u);
-        // upper half: address of key 32 (blk_key_hi) instead of key 0
-        up[r] = (kLe ? v <= x[r] : v < x[r]) ? 4u * (uint32_t)(blk_key_hi(M, k[r]) - blk_key_lo(k[r]))
-                                             : 0u;
-        a[r] = lo + up[r];
+        a[r] = lo + ((kLe ? v <= x[r] : v < x[r]) ? 4u * kBlkUpper : 0u);
     }
 #pragma unroll
     for (int step = 16; step >= 1; step >>= 1) {
@@ -92,11 +91,8 @@ __device__ __forceinline__ void masks_many64(const uint32_t *T, const int (&k)[R
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        // c = (a - lower base) / 4, less the upper half's shift (which is 32 keys + 1)
-        const uint32_t d = 4u * (uint32_t)(blk_pm_off(M, k[r]) - blk_key_lo(k[r]));
-        const uint32_t e = a[r] + d - up[r] + (up[r] ? 128u : 0u);
-        const uint32_t lo = lds_ld(e);
-        const uint32_t hi = lds_ld(e + 4u * 65u);
+        const uint32_t lo = lds_ld(a[r] + 4u * 32u);
+        const uint32_t hi = lds_ld(a[r] + 4u * 65u);
         mask[r] = (uint64_t)lo | ((uint64_t)hi << 32);
     }
 }
@@ -112,12 +108,13 @@ __device__ __forceinline__ uint64_t low_bits(uint32_t c) {
 constexpr int kFwdThreads = 256;
 constexpr int kTJ = 2;                            // points per lane
 constexpr int kTileJ = kFwdThreads * kTJ;         // points per work item
-// Tables staged per work-group: the all-pairs counts take 24 KiB chunks (more
-// resident work-groups per CU: 2.98 ms for both counts at N = 200k, M = 5,
-// against 3.24 ms with 34 KiB and 3.81 ms with 49 KiB); a peeling level's
-// items take 34 KiB (1.77 ms for the peel, against 1.82 ms with 24 KiB).
+// Tables staged per work-group: the all-pairs counts take 24.5 KiB chunks (six
+// M = 5 tables; with the out-degree counters six work-groups stay resident per
+// CU: 2.98 ms for both counts at N = 200k, M = 5 when they were separate
+// passes, against 3.24 ms with 34 KiB and 3.81 ms with 49 KiB); a peeling
+// level's items take 34 KiB (1.77 ms for the peel, against 1.82 ms with 24 KiB).
 #ifndef NSGA3_LDS_COUNT_DWORDS
-#define NSGA3_LDS_COUNT_DWORDS 6240
+#define NSGA3_LDS_COUNT_DWORDS 6264
 #endif
 constexpr int kLdsCountDwords = NSGA3_LDS_COUNT_DWORDS;
 constexpr int kLdsLevelDwords = 8704;
@@ -185,7 +182,7 @@ __device__ __forceinline__ void build_block(const uint32_t *__restrict__ rec, in
             const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)key, m);
             rank += (o < key || (o == key && m < l)) ? 1u : 0u;
         }
-        T[blk_key_slot(M, k, (int)rank)] = key;
+        T[blk_key_slot(k, (int)rank)] = key;
         inv[rank] = l;
         block_sync<kWaveSync>();
         const int mem = inv[l];
@@ -194,12 +191,11 @@ __device__ __forceinline__ void build_block(const uint32_t *__restrict__ rec, in
             const uint64_t t = __shfl_up(bit, o, 64);
             if (l >= o) bit |= t;
         }
-        uint32_t *pm = T + blk_pm_off(M, k);
-        pm[l + 1] = (uint32_t)bit;
-        pm[65 + l + 1] = (uint32_t)(bit >> 32);
+        T[blk_mask_lo(k, l + 1)] = (uint32_t)bit;
+        T[blk_mask_hi(k, l + 1)] = (uint32_t)(bit >> 32);
         if (l == 0) {
-            pm[0] = 0u;
-            pm[65] = 0u;
+            T[blk_mask_lo(k, 0)] = 0u;
+            T[blk_mask_hi(k, 0)] = 0u;
         }
         block_sync<kWaveSync>();
     }
@@ -218,9 +214,10 @@ __device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__re
 
 // Forward: for each of the wave's kTJ x 64 points j (keys kj, run starts run),
 // add the number of members of the staged blocks that dominate j.  With kOut,
-// every dominating member also gains one in its LDS counter oc[b * 64 + bit]
-// (block b of the staged chunk, bit = its index in the block): the same
-// probes then give the out-degrees of the staged members, since every
+// every dominating member also gains one in its LDS counter (member q = b * 64
+// + bit of the staged chunk: the 16-bit half q & 1 of oc[q >> 1]; a work-group
+// adds at most kTilesPerItem * kTileJ < 65536 to one member per chunk): the
+// same probes then give the out-degrees of the staged members, since every
 // dominance pair (i before j's run) is probed exactly once.
 template <int M, int TJ = kTJ, bool kOut = false>
 __device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32_t run_lo,

@@ -47,9 +47,11 @@ inline unsigned build_grid(int64_t nblk) { return (unsigned)nblk; }
 // (1, 2) 2.92, (2, 1) 2.86, (2, 4) 2.93, (3, 2) 2.89, (4, 1) 2.97, (4, 3) 3.06.
 constexpr int kTilesPerItem = 2;
 constexpr int kChunksPerItem = 2;
+static_assert(kTilesPerItem * kTileJ < 65536, "16-bit out-degree counters per chunk");
 
-// LDS out-degree counters of one staged chunk -> global (sorted positions
-// b0 * 64 + q), cleared for the next chunk.
+// LDS out-degree counters of one staged chunk (two 16-bit counters per
+// dword) -> global (sorted positions b0 * 64 + member), cleared for the next
+// chunk.
 __device__ __forceinline__ void flush_out_counts(uint32_t *oc, int32_t b0, int32_t nb,
                                                  int32_t *__restrict__ dom_out) {
     for (int q = threadIdx.x; q < nb * kBlk; q += kFwdThreads) {
@@ -62,7 +64,8 @@ __device__ __forceinline__ void flush_out_counts(uint32_t *oc, int32_t b0, int32
 }
 
 // kOut: out-degrees of the chunk members from the same probes (LDS counters
-// oc[count_chunk * 64], one global atomic per non-zero counter per chunk).
+// oc[count_chunk * 32], two per dword; one global atomic per non-zero counter
+// per chunk).
 template <int M, bool kOut>
 __device__ __forceinline__ void fwd_all_item(const uint32_t *__restrict__ tabs, int32_t nblk,
                                              const uint32_t *__restrict__ recs,

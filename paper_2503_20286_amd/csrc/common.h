@@ -76,4 +76,9 @@ struct GridBar {
 
 struct Ws;  // workspace views, defined in the runtime
 
+// Dwords of one 64-member block-bitset table of an M-objective point list
+// (header and positions, then 195 dwords per objective: keys and prefix
+// masks, laid out in bitdom.h), rounded to whole 16-byte vectors.
+__host__ __device__ constexpr int blk_stride(int M) { return ((68 + 195 * M) + 3) / 4 * 4; }
+
 }  // namespace nsga3

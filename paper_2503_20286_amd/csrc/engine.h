@@ -97,7 +97,7 @@ __host__ __device__ inline ELayout elayout(int64_t N, int M, int H) {
     L.recs = bump(4 * n * MP);
     L.runstart = bump(4 * n);
     L.runend = bump(4 * n);
-    L.tabs = bump(4 * (size_t)cdiv(N, 64) * (size_t)(((68 + 194 * M) + 3) / 4 * 4));
+    L.tabs = bump(4 * (size_t)cdiv(N, 64) * (size_t)blk_stride(M));
     L.din = bump(4 * n);
     L.dout = bump(4 * n);
     L.rank_s = bump(4 * n);
