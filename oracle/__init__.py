@@ -47,6 +47,10 @@ def _declare(L):
     L.oracle_select.argtypes = [P, i64, i32, P, i32, i64, P, P, P, P, P, P, P]
     L.oracle_select_mode.argtypes = [P, i64, i32, P, i32, i64, i32, P, P, P, P, P, P, P]
     L.oracle_num_threads.argtypes = []
+    L.oracle_rvea_gamma.argtypes = [P, i32, i32, P]
+    L.oracle_rvea_gamma.restype = ctypes.c_int
+    L.oracle_rvea_select.argtypes = [P, i64, i32, P, i32, i64, i64, ctypes.c_double, P, P, P, P, P]
+    L.oracle_rvea_select.restype = ctypes.c_int
     L.oracle_set_num_threads.argtypes = [i32]
     L.oracle_set_num_threads.restype = None
     for name in ("oracle_dominates", "oracle_dominance", "oracle_dominance_one", "oracle_ranks",
@@ -240,3 +244,39 @@ def select(objs, refs, K, with_counts=True, niching="exact"):
                                     _ptr(dout), _ptr(info)),
            "oracle_select_mode")
     return Selection(sel, rank, niche, dist, din, dout, *[int(v) for v in info])
+
+
+# ---------------------------------------------------------------------------
+# TensorRVEA environmental selection (Supplementary Sec. S.V, Alg. S.12)
+# ---------------------------------------------------------------------------
+def rvea_gamma(refs):
+    """gamma[H]: smallest angle between each reference vector and any other."""
+    R = np.ascontiguousarray(refs, dtype=np.float32)
+    g = np.zeros(R.shape[0], np.float64)
+    _check(lib().oracle_rvea_gamma(_ptr(R), R.shape[0], R.shape[1], _ptr(g)), "oracle_rvea_gamma")
+    return g
+
+
+@dataclass
+class RveaSelection:
+    elite: np.ndarray    # int32[H]: the partition's smallest-APD point, -1 if empty
+    assign: np.ndarray   # int32[N]: partition (reference with the smallest angle)
+    apd: np.ndarray      # float64[N]: angle-penalized distance
+    theta: np.ndarray    # float64[N]: angle to the own reference
+    gap: np.ndarray      # float64[H]: relative gap between the two smallest APDs
+
+
+def rvea_select(objs, refs, t, t_max, alpha=2.0):
+    f = _objs(objs)
+    N, M = f.shape
+    R = np.ascontiguousarray(refs, dtype=np.float32)
+    H = R.shape[0]
+    elite = np.zeros(H, np.int32)
+    assign = np.zeros(N, np.int32)
+    apd = np.zeros(N, np.float64)
+    theta = np.zeros(N, np.float64)
+    gap = np.zeros(H, np.float64)
+    _check(lib().oracle_rvea_select(_ptr(f), N, M, _ptr(R), H, int(t), int(t_max), float(alpha),
+                                    _ptr(elite), _ptr(assign), _ptr(apd), _ptr(theta), _ptr(gap)),
+           "oracle_rvea_select")
+    return RveaSelection(elite, assign, apd, theta, gap)

@@ -5,13 +5,13 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "oracle.c")
+SRCS = [os.path.join(HERE, f) for f in ("oracle.c", "rvea.c")]
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-shared", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter", SRC, "-o",
+           "-shared", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter", *SRCS, "-o",
            LIB_PATH + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))
