@@ -54,6 +54,8 @@ def parse():
                     help="skip the many-objective float32 / bfloat16 comparison")
     ap.add_argument("--no-oneshot", action="store_true",
                     help="skip the one-shot niching report")
+    ap.add_argument("--no-rvea", action="store_true",
+                    help="skip the TensorRVEA selection report")
     ap.add_argument("--assoc", default="fp32", choices=["fp32", "bf16"],
                     help="association screening precision (re-scoring is float64 in both)")
     ap.add_argument("--no-batch", action="store_true",
@@ -221,6 +223,47 @@ def oneshot_report(args, w, objs, refs, g_exact, ref):
         **{f"{k}_{m}": v for k, d in cov.items() for m, v in d.items()},
     }
     return out
+
+
+def rvea_report(args, w, objs, refs):
+    """TensorRVEA selection (Supplementary Alg. S.12) on the same workload:
+    time per call, its screening rate against the float32 vector peak, and
+    parity with the float64 oracle (partitions exact; elites exact outside
+    APD near-ties)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2503_20286_amd as nsga3
+    t, t_max, alpha = 5, 10, 2.0
+    ctx = nsga3.Context(0)
+    r = nsga3.rvea_select(objs, refs, t, t_max, alpha, ctx=ctx)
+    for _ in range(args.warmup):
+        nsga3.rvea_select(objs, refs, t, t_max, alpha, ctx=ctx)
+    ms = _time_calls(lambda: nsga3.rvea_select(objs, refs, t, t_max, alpha, ctx=ctx), args.steps,
+                     torch.cuda.current_stream())
+    r = nsga3.rvea_select(objs, refs, t, t_max, alpha, ctx=ctx)
+    torch.cuda.synchronize()
+    e, a, apd = r.elite.cpu().numpy(), r.assign.cpu().numpy(), r.apd.cpu().numpy()
+    ctx.close()
+    s = oracle.rvea_select(w.objs, w.refs, t, t_max, alpha)
+    tie = s.gap < 1e-12
+    # screening: two float32 passes of H dot products of length M per point
+    flops = 2.0 * 2.0 * w.N * w.H * w.M
+    return {
+        "t": t, "t_max": t_max, "alpha": alpha,
+        "ms_per_selection": ms,
+        "points_per_s": w.N / (ms / 1e3),
+        "screen_tflop_s": flops / (ms / 1e3) / 1e12,
+        "screen_frac_of_fp32_peak": flops / (ms / 1e3) / 157.3e12,
+        "parity": {
+            "assign_mismatch": int(np.sum(a != s.assign)),
+            "elite_mismatch_outside_ties": int(np.sum((e != s.elite) & ~tie)),
+            "max_rel_apd_err": float(np.max(np.abs(apd - s.apd) / np.maximum(s.apd, 1e-300))),
+            "apd_near_tie_partitions": int(np.sum(tie)),
+        },
+        "nonempty_partitions": int(np.sum(e >= 0)),
+    }
 
 
 def c5_report(args):
@@ -496,6 +539,8 @@ def main():
         res["parity"] = parity(w, g, ref)
     if not args.no_oneshot:
         res["oneshot_niching"] = oneshot_report(args, w, objs, refs, g, ref)
+    if not args.no_rvea:
+        res["rvea"] = rvea_report(args, w, objs, refs)
     if not args.no_c5 and args.workload == "large":
         res["c5"] = c5_report(args)
     print(json.dumps(res), flush=True)

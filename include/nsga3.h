@@ -148,6 +148,39 @@ nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t 
                           hipStream_t stream);
 
 /*
+ * Environmental selection of TensorRVEA (Supplementary Sec. S.V, Alg. S.12):
+ * one elite per reference vector by the angle-penalized distance.  With
+ * z = the per-objective minimum over all N points and F' = F - z, every
+ * point joins the partition of the reference with the smallest angle theta
+ * to F' (the largest F'.V_j / ||V_j||, lowest j on ties); gamma_j is the
+ * smallest angle between V_j and another reference;
+ *   APD_i = (1 + M (t / t_max)^alpha theta_i / gamma_{a_i}) ||F'_i||
+ * (the penalty factor computed on the host in float64); elite_j is the point
+ * of partition j with the smallest APD (lowest index on ties), -1 when the
+ * partition is empty.  A point equal to z joins partition 0 with APD 0.
+ *
+ *   objs    DEVICE float[N*M]  objective values, row-major, minimised
+ *   N, M    1 <= N <= 2^31-1, 2 <= M <= 16
+ *   refs    DEVICE float[H*M]  reference vectors (rows >= 0, non-zero, distinct
+ *                              directions), 2 <= H <= 65535
+ *   t, t_max, alpha            generation counter (t >= 0, t_max >= 1) and the rate of
+ *                              change of the penalty (finite, >= 0)
+ *   elite   DEVICE int32[H]    required: elite of every partition, or -1
+ *   assign  DEVICE int32[N]    optional: partition of every point
+ *   apd     DEVICE double[N]   optional: angle-penalized distance of every point
+ *   info    DEVICE nsga3_info* optional: only status (and reserved) are set
+ * Host-checkable errors return NSGA3_E_INVALID and enqueue nothing; a
+ * non-finite objective, an invalid reference row or two references with the
+ * same direction (gamma = 0) set info.status = NSGA3_E_NONFINITE on the
+ * device, and elite is then undefined.  Uses the context's workspace (grown
+ * on demand; nsga3_reserve does not size it).  Asynchronous on `stream`.
+ */
+nsga3_status nsga3_rvea_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t M,
+                               const float *refs, int32_t H, int64_t t, int64_t t_max, double alpha,
+                               int32_t *elite, int32_t *assign, double *apd, nsga3_info *info,
+                               hipStream_t stream);
+
+/*
  * Allocation-free form of nsga3_select, for callers that cannot allocate
  * device memory (code under HIP graph capture, serving loops, harnesses that
  * forbid hipMalloc).  Same arguments, outputs and results as nsga3_select with

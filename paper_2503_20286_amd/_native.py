@@ -90,6 +90,9 @@ def load():
         L.nsga3_select.restype = ctypes.c_int
         L.nsga3_select_noalloc.argtypes = [P, i64, i32, P, i32, i64, P, P, P, P, P, P, P, P]
         L.nsga3_select_noalloc.restype = ctypes.c_int
+        L.nsga3_rvea_select.argtypes = [P, P, i64, i32, P, i32, i64, i64, ctypes.c_double, P, P, P,
+                                        P, P]
+        L.nsga3_rvea_select.restype = ctypes.c_int
         L.nsga3_status_string.argtypes = [ctypes.c_int]
         L.nsga3_status_string.restype = ctypes.c_char_p
         L.nsga3_profile.argtypes = [P, ctypes.c_int]
@@ -335,6 +338,49 @@ def select_noalloc(objs, refs, K: int, *, out: Selection, stream=None) -> Select
                                 ctypes.c_void_p(s.cuda_stream))
     if rc != 0:
         raise NativeError("nsga3_select_noalloc", rc, L)
+    return out
+
+
+@dataclass
+class RveaSelection:
+    elite: "object"      # int32[H]
+    assign: "object"     # int32[N]
+    apd: "object"        # float64[N]
+    info_raw: "object"
+
+    def info(self) -> Info:
+        v = [int(x) for x in self.info_raw.cpu().tolist()]
+        return Info(*v)
+
+
+def rvea_select(objs, refs, t: int, t_max: int, alpha: float = 2.0, *,
+                ctx: Optional[Context] = None, stream=None) -> RveaSelection:
+    """TensorRVEA environmental selection (nsga3_rvea_select): the elite of
+    every reference vector's partition by angle-penalized distance."""
+    import torch
+    _check_tensor(objs, "objs", 2)
+    _check_tensor(refs, "refs", 2)
+    N, M = objs.shape
+    H = refs.shape[0]
+    if refs.shape[1] != M:
+        raise ValueError("refs must have M columns")
+    dev = objs.device
+    if ctx is None:
+        ctx = default_context(dev.index if dev.index is not None else torch.cuda.current_device())
+    out = RveaSelection(elite=torch.empty(H, dtype=torch.int32, device=dev),
+                        assign=torch.empty(N, dtype=torch.int32, device=dev),
+                        apd=torch.empty(N, dtype=torch.float64, device=dev),
+                        info_raw=torch.zeros(8, dtype=torch.int32, device=dev))
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+
+    def p(t_):
+        return ctypes.c_void_p(t_.data_ptr())
+
+    rc = ctx._lib.nsga3_rvea_select(ctx.handle, p(objs), int(N), int(M), p(refs), int(H), int(t),
+                                    int(t_max), float(alpha), p(out.elite), p(out.assign),
+                                    p(out.apd), p(out.info_raw), ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise NativeError("nsga3_rvea_select", rc, ctx._lib)
     return out
 
 

@@ -4,6 +4,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <math.h>
+
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -612,6 +614,35 @@ nsga3_status nsga3_select_noalloc(const float *objs, int64_t N, int32_t M, const
     const nsga3_problem p = {objs, N, M, refs, H, K, selected, rank, niche, dist,
                              dom_in, dom_out, info};
     return enqueue_select(a, p, stream) == hipSuccess ? NSGA3_OK : NSGA3_E_HIP;
+}
+
+nsga3_status nsga3_rvea_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t M,
+                               const float *refs, int32_t H, int64_t t, int64_t t_max, double alpha,
+                               int32_t *elite, int32_t *assign, double *apd, nsga3_info *info,
+                               hipStream_t stream) {
+    if (!ctx || !objs || !refs || !elite) return NSGA3_E_INVALID;
+    if (N < 1 || N > 2147483647LL || M < 2 || M > 16 || H < 2 || H > 65535) return NSGA3_E_INVALID;
+    if (t < 0 || t_max < 1 || !(alpha >= 0.0) || !isfinite(alpha)) return NSGA3_E_INVALID;
+    DeviceGuard g(ctx->device);
+    const nsga3_status st = ensure_ws(ctx, rvea_workspace_bytes(N, M, H));
+    if (st != NSGA3_OK) return st;
+    RveaViews v;
+    v.objs = objs;
+    v.N = N;
+    v.M = M;
+    v.refs = refs;
+    v.H = H;
+    v.penalty = (double)M * pow((double)t / (double)t_max, alpha);
+    v.elite = elite;
+    v.assign = assign;
+    v.apd = apd;
+    v.info = info;
+    v.ws = ctx->ws;
+    if (run_rvea(v, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return NSGA3_E_HIP;
+    }
+    return NSGA3_OK;
 }
 
 static bool problem_ok(const nsga3_problem &p) {

@@ -243,6 +243,7 @@ __device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32
                 x[t * M + k] = kj[t][k];
             }
         masks_many64<M, TJ * M, true>(T, ko, x, pm);
+        uint64_t mt[TJ];
 #pragma unroll
         for (int t = 0; t < TJ; ++t) {
             uint64_t m = ~0ull;
@@ -255,13 +256,24 @@ __device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32
 #pragma unroll
             for (int k = 0; k < M; ++k) m &= pm[t * M + k];
             cnt[t] += __popcll(m);
-            if constexpr (kOut) {
-                uint32_t *ob = oc + b * kBlk;
-                while (m) {
-                    const uint32_t bit = (uint32_t)__builtin_ctzll(m);
-                    __hip_atomic_fetch_add(ob + bit, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    m &= m - 1ull;
-                }
+            mt[t] = m;
+        }
+        if constexpr (kOut) {
+            // one pass over the union of the lane's masks: a member that
+            // dominates several of the lane's points is added once with their
+            // number (the lane's points are neighbours in the sort, so they
+            // share many dominators)
+            uint32_t *ob = oc + b * kBlk;
+            uint64_t u = 0ull;
+#pragma unroll
+            for (int t = 0; t < TJ; ++t) u |= mt[t];
+            while (u) {
+                const uint32_t bit = (uint32_t)__builtin_ctzll(u);
+                uint32_t n = 0;
+#pragma unroll
+                for (int t = 0; t < TJ; ++t) n += (uint32_t)(mt[t] >> bit) & 1u;
+                __hip_atomic_fetch_add(ob + bit, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                u &= u - 1ull;
             }
         }
     }

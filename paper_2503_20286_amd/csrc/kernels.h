@@ -87,6 +87,24 @@ hipError_t run_peel(const SortViews &v, const LaunchCfg &cfg, hipStream_t s);
 int peel_max_blocks_per_cu(int M);
 size_t split_state_entries(int64_t N);
 
+// ---- rvea.hip -------------------------------------------------------------
+// TensorRVEA angle-penalized distance selection (one elite per reference).
+struct RveaViews {
+    const float *objs;
+    int64_t N;
+    int M;
+    const float *refs;
+    int H;
+    double penalty;              // M (t / t_max)^alpha, computed on the host
+    int32_t *elite;              // [H]
+    int32_t *assign;             // [N] or null (then in the workspace)
+    double *apd;                 // [N] or null (then in the workspace)
+    nsga3_info *info;            // or null
+    void *ws;                    // rvea_workspace_bytes(N, M, H)
+};
+size_t rvea_workspace_bytes(int64_t N, int M, int H);
+hipError_t run_rvea(const RveaViews &v, hipStream_t s);
+
 // ---- select.hip -----------------------------------------------------------
 size_t oneshot_temp_bytes(int64_t n);   // workspace temp needed by the one-shot niching
 struct SelectViews {
