@@ -47,6 +47,12 @@ def _declare(L):
     L.oracle_select.argtypes = [P, i64, i32, P, i32, i64, P, P, P, P, P, P, P]
     L.oracle_select_mode.argtypes = [P, i64, i32, P, i32, i64, i32, P, P, P, P, P, P, P]
     L.oracle_num_threads.argtypes = []
+    L.oracle_hype_alpha.argtypes = [i64, i64, P]
+    L.oracle_hype_alpha.restype = ctypes.c_int
+    L.oracle_hype_hv.argtypes = [P, i64, i32, P, P, i64, i64, P, P]
+    L.oracle_hype_hv.restype = ctypes.c_int
+    L.oracle_hype_select.argtypes = [P, i64, i32, P, P, i64, i64, P, P, P, P]
+    L.oracle_hype_select.restype = ctypes.c_int
     L.oracle_rvea_gamma.argtypes = [P, i32, i32, P]
     L.oracle_rvea_gamma.restype = ctypes.c_int
     L.oracle_rvea_select.argtypes = [P, i64, i32, P, i32, i64, i64, ctypes.c_double, P, P, P, P, P]
@@ -280,3 +286,51 @@ def rvea_select(objs, refs, t, t_max, alpha=2.0):
                                     _ptr(elite), _ptr(assign), _ptr(apd), _ptr(theta), _ptr(gap)),
            "oracle_rvea_select")
     return RveaSelection(elite, assign, apd, theta, gap)
+
+
+# ---------------------------------------------------------------------------
+# TensorHypE environmental selection (Sec. IV-C; Supplementary Alg. S.10/S.11)
+# ---------------------------------------------------------------------------
+def hype_alpha(k, N):
+    """alpha_c for c = 1..k (float64[k])."""
+    a = np.zeros(max(int(k), 1), np.float64)
+    _check(lib().oracle_hype_alpha(int(k), int(N), _ptr(a)), "oracle_hype_alpha")
+    return a[:int(k)]
+
+
+def hype_hv(objs, vref, U, k):
+    """(HV estimate float64[N], sample dominance counts int32[s]) for a given k."""
+    f = _objs(objs)
+    N, M = f.shape
+    v = np.ascontiguousarray(vref, dtype=np.float32)
+    u = np.ascontiguousarray(U, dtype=np.float32)
+    hv = np.zeros(N, np.float64)
+    cnt = np.zeros(u.shape[0], np.int32)
+    _check(lib().oracle_hype_hv(_ptr(f), N, M, _ptr(v), _ptr(u), u.shape[0], int(k), _ptr(hv),
+                                _ptr(cnt)), "oracle_hype_hv")
+    return hv, cnt
+
+
+@dataclass
+class HypeSelection:
+    selected: np.ndarray   # int32[n], ascending
+    d: np.ndarray          # float64[N]: HV estimate for rank <= l, -inf elsewhere
+    rank: np.ndarray
+    last_front: int
+    num_fronts: int
+    k: int
+    last_front_size: int
+
+
+def hype_select(objs, vref, U, n):
+    f = _objs(objs)
+    N, M = f.shape
+    v = np.ascontiguousarray(vref, dtype=np.float32)
+    u = np.ascontiguousarray(U, dtype=np.float32)
+    sel = np.zeros(int(n), np.int32)
+    d = np.zeros(N, np.float64)
+    rank = np.zeros(N, np.int32)
+    info = np.zeros(4, np.int64)
+    _check(lib().oracle_hype_select(_ptr(f), N, M, _ptr(v), _ptr(u), u.shape[0], int(n), _ptr(sel),
+                                    _ptr(d), _ptr(rank), _ptr(info)), "oracle_hype_select")
+    return HypeSelection(sel, d, rank, *[int(x) for x in info])
