@@ -56,6 +56,8 @@ def parse():
                     help="skip the one-shot niching report")
     ap.add_argument("--no-rvea", action="store_true",
                     help="skip the TensorRVEA selection report")
+    ap.add_argument("--no-hype", action="store_true",
+                    help="skip the TensorHypE selection report")
     ap.add_argument("--assoc", default="fp32", choices=["fp32", "bf16"],
                     help="association screening precision (re-scoring is float64 in both)")
     ap.add_argument("--no-batch", action="store_true",
@@ -264,6 +266,56 @@ def rvea_report(args, w, objs, refs):
         },
         "nonempty_partitions": int(np.sum(e >= 0)),
     }
+
+
+def hype_report(args):
+    """TensorHypE selection (Sec. IV-C; Supplementary Alg. S.10, S.11): the
+    ties workload (N = 20,000 merged points of a population of 10,000, M = 3)
+    with 10,000 Monte Carlo draws, timed and compared with the oracle; and
+    the large workload (N = 200,000, M = 5) timed."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2503_20286_amd as nsga3
+    import workloads
+    out = {}
+    for name, check in (("ties", True), ("large", False)):
+        w = workloads.make(name)
+        s = 10_000
+        U = np.random.default_rng(2024).random((s, w.M)).astype(np.float32)
+        vref = (w.objs.max(0).astype(np.float64) * 1.1 + 0.01).astype(np.float32)
+        o = torch.from_numpy(w.objs).cuda()
+        v = torch.from_numpy(vref).cuda()
+        u = torch.from_numpy(U).cuda()
+        n = w.N // 2
+        ctx = nsga3.Context(0)
+        r = nsga3.hype_select(o, v, u, n, ctx=ctx)
+        for _ in range(args.warmup):
+            nsga3.hype_select(o, v, u, n, ctx=ctx)
+        ms = _time_calls(lambda: nsga3.hype_select(o, v, u, n, ctx=ctx), args.steps,
+                         torch.cuda.current_stream())
+        r = nsga3.hype_select(o, v, u, n, ctx=ctx)
+        torch.cuda.synchronize()
+        info = r.info()
+        rec = {"workload": f"{name}: N={w.N} M={w.M} n={n} s={s}", "ms_per_selection": ms,
+               "points_per_s": w.N / (ms / 1e3), "last_front": info.last_front,
+               "last_front_size": info.last_front_size,
+               "sample_point_tests_per_s": float(s) * w.N / (ms / 1e3)}
+        if check:
+            sel = r.selected.cpu().numpy()
+            d = r.d.cpu().numpy()
+            ref = oracle.hype_select(w.objs, vref, U, n)
+            S = ref.rank <= ref.last_front
+            rec["parity"] = {
+                "rank_mismatch": int(np.sum(r.rank.cpu().numpy() != ref.rank)),
+                "selected_mismatch": int(np.setxor1d(sel, ref.selected).size),
+                "max_rel_hv_err": float(np.max(np.abs(d[S] - ref.d[S]) /
+                                               np.maximum(np.abs(ref.d[S]), 1e-300))),
+            }
+        ctx.close()
+        out[name] = rec
+    return out
 
 
 def c5_report(args):
@@ -541,6 +593,8 @@ def main():
         res["oneshot_niching"] = oneshot_report(args, w, objs, refs, g, ref)
     if not args.no_rvea:
         res["rvea"] = rvea_report(args, w, objs, refs)
+    if not args.no_hype and args.workload == "large":
+        res["hype"] = hype_report(args)
     if not args.no_c5 and args.workload == "large":
         res["c5"] = c5_report(args)
     print(json.dumps(res), flush=True)

@@ -148,6 +148,39 @@ nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t 
                           hipStream_t stream);
 
 /*
+ * Environmental selection of TensorHypE (Sec. IV-C; Supplementary Alg. S.10,
+ * S.11): the nondominated sort of nsga3_select gives ranks r and the last
+ * admitted front l for a population of n; every point of r < l is kept, and
+ * the members of F_l with the largest Monte Carlo hypervolume estimates fill
+ * the remaining places (lowest index among equal estimates).  Estimation
+ * over all N points (as printed): k = |{r <= l}| - n,
+ * alpha_c = (1/c) prod_{i=1}^{c-1} (k - i) / (N - i); f_l = the per-objective
+ * minimum; sample i = f_l + U_i (vref - f_l), rounded to float32;
+ * count_i = #{p : F_p <= sample i in every objective};
+ * HV_p = V / s * sum over the samples p dominates with count_i <= k of
+ * alpha_{count_i}, V = prod_j (vref_j - f_l,j).
+ *
+ *   objs      DEVICE float[N*M]  objective values, row-major, minimised (2 <= M <= 16)
+ *   vref      DEVICE float[M]    reference point (the upper corner of the sampling box)
+ *   U         DEVICE float[s*M]  the caller's uniform draws in [0, 1), row-major
+ *   s         1 <= s <= 2^31-1   number of samples
+ *   n         1 <= n <= N        population size to keep
+ *   selected  DEVICE int32[n]    required: kept indices, ascending
+ *   d         DEVICE double[N]   optional: HV estimate for rank <= l, -inf elsewhere
+ *   rank      DEVICE int32[N]    optional: 0-based front index
+ *   info      DEVICE nsga3_info* optional: status and front statistics
+ * Host-checkable errors return NSGA3_E_INVALID and enqueue nothing; non-finite
+ * objectives, draws or reference point set info.status = NSGA3_E_NONFINITE.
+ * The estimates are float64; the alpha products are formed in chunks, so they
+ * may differ from a sequential product in the last bits.  Uses the context's
+ * workspace (grown on demand).  Asynchronous on `stream`.
+ */
+nsga3_status nsga3_hype_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t M,
+                               const float *vref, const float *U, int64_t s, int64_t n,
+                               int32_t *selected, double *d, int32_t *rank, nsga3_info *info,
+                               hipStream_t stream);
+
+/*
  * Environmental selection of TensorRVEA (Supplementary Sec. S.V, Alg. S.12):
  * one elite per reference vector by the angle-penalized distance.  With
  * z = the per-objective minimum over all N points and F' = F - z, every

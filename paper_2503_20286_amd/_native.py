@@ -92,6 +92,8 @@ def load():
         L.nsga3_select_noalloc.restype = ctypes.c_int
         L.nsga3_rvea_select.argtypes = [P, P, i64, i32, P, i32, i64, i64, ctypes.c_double, P, P, P,
                                         P, P]
+        L.nsga3_hype_select.argtypes = [P, P, i64, i32, P, P, i64, i64, P, P, P, P, P]
+        L.nsga3_hype_select.restype = ctypes.c_int
         L.nsga3_rvea_select.restype = ctypes.c_int
         L.nsga3_status_string.argtypes = [ctypes.c_int]
         L.nsga3_status_string.restype = ctypes.c_char_p
@@ -381,6 +383,50 @@ def rvea_select(objs, refs, t: int, t_max: int, alpha: float = 2.0, *,
                                     p(out.apd), p(out.info_raw), ctypes.c_void_p(s.cuda_stream))
     if rc != 0:
         raise NativeError("nsga3_rvea_select", rc, ctx._lib)
+    return out
+
+
+@dataclass
+class HypeSelection:
+    selected: "object"   # int32[n], ascending
+    d: "object"          # float64[N]: HV estimate for rank <= l, -inf elsewhere
+    rank: "object"       # int32[N]
+    info_raw: "object"
+
+    def info(self) -> Info:
+        v = [int(x) for x in self.info_raw.cpu().tolist()]
+        return Info(*v)
+
+
+def hype_select(objs, vref, U, n: int, *, ctx: Optional[Context] = None,
+                stream=None) -> HypeSelection:
+    """TensorHypE environmental selection (nsga3_hype_select): keep n of the
+    N rows of ``objs``, the last front by Monte Carlo hypervolume estimates
+    from the caller's uniform draws ``U`` (s x M) and reference point ``vref``."""
+    import torch
+    _check_tensor(objs, "objs", 2)
+    _check_tensor(U, "U", 2)
+    _check_tensor(vref, "vref", 1)
+    N, M = objs.shape
+    if U.shape[1] != M or vref.shape[0] != M:
+        raise ValueError("U must have M columns and vref M entries")
+    dev = objs.device
+    if ctx is None:
+        ctx = default_context(dev.index if dev.index is not None else torch.cuda.current_device())
+    out = HypeSelection(selected=torch.empty(int(n), dtype=torch.int32, device=dev),
+                        d=torch.empty(N, dtype=torch.float64, device=dev),
+                        rank=torch.empty(N, dtype=torch.int32, device=dev),
+                        info_raw=torch.zeros(8, dtype=torch.int32, device=dev))
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+
+    def p(t_):
+        return ctypes.c_void_p(t_.data_ptr())
+
+    rc = ctx._lib.nsga3_hype_select(ctx.handle, p(objs), int(N), int(M), p(vref), p(U),
+                                    int(U.shape[0]), int(n), p(out.selected), p(out.d), p(out.rank),
+                                    p(out.info_raw), ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise NativeError("nsga3_hype_select", rc, ctx._lib)
     return out
 
 

@@ -11,8 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libnsga3.so")
-SOURCES = ["api.hip", "bitdom.hip", "dominance.hip", "engine.hip", "peel.hip", "rvea.hip",
-           "select.hip", "sort_scan.hip"]
+SOURCES = ["api.hip", "bitdom.hip", "dominance.hip", "engine.hip", "hype.hip", "peel.hip",
+           "rvea.hip", "select.hip", "sort_scan.hip"]
 ARCH = "gfx950"
 
 

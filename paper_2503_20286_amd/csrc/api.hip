@@ -239,38 +239,15 @@ struct EnqArgs {
     volatile int32_t *last_fronts;    // pinned slot for the front count, or null
 };
 
-// Enqueues one whole selection on `stream` using the workspace at a.ws (sized
-// by layout_for for the problem).  Allocates nothing; safe to capture.
-hipError_t enqueue_select(const EnqArgs &a, const nsga3_problem &p, hipStream_t stream) {
-    const float *objs = p.objs, *refs = p.refs;
-    const int64_t N = p.N, K = p.K;
-    const int32_t M = p.M, H = p.H;
-    int32_t *selected = p.selected, *rank = p.rank, *niche = p.niche;
-    float *dist = p.dist;
-    int32_t *dom_in = p.dom_in, *dom_out = p.dom_out;
-    nsga3_info *info = p.info;
-    const Layout L = layout_for(N, M, H, kGridCap);
-    char *w = a.ws;
+// Views of the sort stage (a0-a3) over the workspace w carved by L.
+SortViews sort_views(char *w, const Layout &L, const nsga3_problem &p, int32_t *rank_o,
+                     const Marker &mk, const LaunchCfg &cfg) {
 #define WS(T, f) reinterpret_cast<T *>(w + L.f)
+    const float *objs = p.objs;
+    const int64_t N = p.N, K = p.K;
+    const int32_t M = p.M;
+    int32_t *dom_in = p.dom_in, *dom_out = p.dom_out;
     DevScalars *sc = WS(DevScalars, sc);
-    int32_t *rank_o = rank ? rank : WS(int32_t, rank);
-    int32_t *niche_o = niche ? niche : WS(int32_t, niche);
-
-    PhaseMarks marks(a.marks, stream);
-    Marker mk;
-    mk.fn = [](void *x) { static_cast<PhaseMarks *>(x)->mark(); };
-    mk.arg = &marks;
-    marks.mark();
-    int32_t *zero_p[] = {WS(int32_t, dom_in_s), WS(int32_t, dom_out_s), WS(int32_t, rho),
-                         WS(int32_t, bcount), WS(int32_t, bar), WS(int32_t, work),
-                         WS(int32_t, lbstate)};
-    const int64_t zero_n[] = {N, N, H, H, (int64_t)(sizeof(GridBar) / sizeof(int32_t)),
-                              kMaxHostLevels, (int64_t)(2 * L.lb_stride)};
-    hipError_t e = run_init(sc, zero_p, zero_n, 7, stream);
-    if (e == hipSuccess)
-        e = run_refs(refs, H, M, WS(double, rhat64), WS(float, rhat32), WS(uint16_t, rhat16), sc,
-                     stream);
-
     SortViews sv;
     sv.objs = objs;
     sv.N = N;
@@ -309,7 +286,44 @@ hipError_t enqueue_select(const EnqArgs &a, const nsga3_problem &p, hipStream_t 
     sv.sc = sc;
     sv.bar = WS(GridBar, bar);
     sv.mark = mk;
-    sv.out_mode = a.cfg.out_mode;
+    sv.out_mode = cfg.out_mode;
+#undef WS
+    return sv;
+}
+
+// Enqueues one whole selection on `stream` using the workspace at a.ws (sized
+// by layout_for for the problem).  Allocates nothing; safe to capture.
+hipError_t enqueue_select(const EnqArgs &a, const nsga3_problem &p, hipStream_t stream) {
+    const float *objs = p.objs, *refs = p.refs;
+    const int64_t N = p.N, K = p.K;
+    const int32_t M = p.M, H = p.H;
+    int32_t *selected = p.selected, *rank = p.rank, *niche = p.niche;
+    float *dist = p.dist;
+    int32_t *dom_in = p.dom_in, *dom_out = p.dom_out;
+    nsga3_info *info = p.info;
+    const Layout L = layout_for(N, M, H, kGridCap);
+    char *w = a.ws;
+#define WS(T, f) reinterpret_cast<T *>(w + L.f)
+    DevScalars *sc = WS(DevScalars, sc);
+    int32_t *rank_o = rank ? rank : WS(int32_t, rank);
+    int32_t *niche_o = niche ? niche : WS(int32_t, niche);
+
+    PhaseMarks marks(a.marks, stream);
+    Marker mk;
+    mk.fn = [](void *x) { static_cast<PhaseMarks *>(x)->mark(); };
+    mk.arg = &marks;
+    marks.mark();
+    int32_t *zero_p[] = {WS(int32_t, dom_in_s), WS(int32_t, dom_out_s), WS(int32_t, rho),
+                         WS(int32_t, bcount), WS(int32_t, bar), WS(int32_t, work),
+                         WS(int32_t, lbstate)};
+    const int64_t zero_n[] = {N, N, H, H, (int64_t)(sizeof(GridBar) / sizeof(int32_t)),
+                              kMaxHostLevels, (int64_t)(2 * L.lb_stride)};
+    hipError_t e = run_init(sc, zero_p, zero_n, 7, stream);
+    if (e == hipSuccess)
+        e = run_refs(refs, H, M, WS(double, rhat64), WS(float, rhat32), WS(uint16_t, rhat16), sc,
+                     stream);
+
+    SortViews sv = sort_views(w, L, p, rank_o, mk, a.cfg);
     const LaunchCfg &cfg = a.cfg;
     if (e == hipSuccess) e = run_sort_stage(sv, cfg, stream);
     if (e == hipSuccess && a.last_fronts)
@@ -614,6 +628,72 @@ nsga3_status nsga3_select_noalloc(const float *objs, int64_t N, int32_t M, const
     const nsga3_problem p = {objs, N, M, refs, H, K, selected, rank, niche, dist,
                              dom_in, dom_out, info};
     return enqueue_select(a, p, stream) == hipSuccess ? NSGA3_OK : NSGA3_E_HIP;
+}
+
+nsga3_status nsga3_hype_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t M,
+                               const float *vref, const float *U, int64_t s, int64_t n,
+                               int32_t *selected, double *d, int32_t *rank, nsga3_info *info,
+                               hipStream_t stream) {
+    if (!ctx || !objs || !vref || !U || !selected) return NSGA3_E_INVALID;
+    if (!sizes_ok(N, M, 1) || n < 1 || n > N || s < 1 || s > 2147483647LL) return NSGA3_E_INVALID;
+    DeviceGuard g(ctx->device);
+    const Layout L = layout_for(N, M, 1, kGridCap);
+    const size_t extra = hype_extra_bytes(N, M, s);
+    const nsga3_status st = ensure_ws(ctx, L.total + extra);
+    if (st != NSGA3_OK) return st;
+    char *w = (char *)ctx->ws;
+#define WS(T, f) reinterpret_cast<T *>(w + L.f)
+    DevScalars *sc = WS(DevScalars, sc);
+    int32_t *rank_o = rank ? rank : WS(int32_t, rank);
+    const LaunchCfg cfg = ctx_cfg(ctx, M);
+    PhaseMarks marks(nullptr, stream);   // phase timing covers nsga3_select only
+    Marker mk;
+    mk.fn = [](void *x) { static_cast<PhaseMarks *>(x)->mark(); };
+    mk.arg = &marks;
+    int32_t *zero_p[] = {WS(int32_t, dom_in_s), WS(int32_t, dom_out_s), WS(int32_t, bar),
+                         WS(int32_t, work), WS(int32_t, lbstate)};
+    const int64_t zero_n[] = {N, N, (int64_t)(sizeof(GridBar) / sizeof(int32_t)), kMaxHostLevels,
+                              (int64_t)(2 * L.lb_stride)};
+    hipError_t e = run_init(sc, zero_p, zero_n, 5, stream);
+    // ranks and the last front for a population of n (no out-degrees needed)
+    const nsga3_problem p = {objs, N, M, vref, 1, n, selected, rank_o, nullptr, nullptr,
+                             nullptr, nullptr, nullptr};
+    SortViews sv = sort_views(w, L, p, rank_o, mk, cfg);
+    if (e == hipSuccess) e = run_sort_stage(sv, cfg, stream);
+    if (e == hipSuccess && ctx->last_fronts)
+        e = hipMemcpyAsync((void *)ctx->last_fronts, &sc->num_fronts, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess && !cfg.bitsets) e = run_build_all_tables(sv, stream);
+    if (e == hipSuccess) {
+        HypeViews hv;
+        hv.objs = objs;
+        hv.N = N;
+        hv.M = M;
+        hv.n = n;
+        hv.vref = vref;
+        hv.U = U;
+        hv.s = s;
+        hv.selected = selected;
+        hv.d = d;
+        hv.rank = rank_o;
+        hv.tabs_all = WS(uint32_t, tabs_all);
+        hv.skey = WS(uint64_t, skey);
+        hv.skey_alt = WS(uint64_t, skey_alt);
+        hv.sval = WS(uint32_t, sval);
+        hv.sval_alt = WS(uint32_t, sval_alt);
+        hv.temp = WS(uint32_t, temp);
+        hv.selflag = WS(uint8_t, selflag);
+        hv.sc = sc;
+        hv.info = info;
+        hv.extra = w + L.total;
+        e = run_hype(hv, stream);
+    }
+#undef WS
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return NSGA3_E_HIP;
+    }
+    return NSGA3_OK;
 }
 
 nsga3_status nsga3_rvea_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t M,

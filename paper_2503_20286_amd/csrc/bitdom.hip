@@ -460,6 +460,26 @@ static hipError_t launch_counts(const SortViews &v, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int M>
+static hipError_t launch_build_all(const SortViews &v, hipStream_t s) {
+    const int32_t N = (int32_t)v.N;
+    const int32_t nblk = (N + kBlk - 1) / kBlk;
+    hipLaunchKernelGGL(k_build_blocks<M>, dim3(build_grid(nblk)), dim3(kBuildWaves * kWave), 0, s, v.recs,
+                       N, (const int32_t *)nullptr, v.tabs_all, v.sc);
+    return hipGetLastError();
+}
+
+hipError_t run_build_all_tables(const SortViews &v, hipStream_t s) {
+    switch (v.M) {
+#define NSGA3_CASE(m) case m: return launch_build_all<m>(v, s);
+        NSGA3_CASE(2) NSGA3_CASE(3) NSGA3_CASE(4) NSGA3_CASE(5) NSGA3_CASE(6) NSGA3_CASE(7)
+        NSGA3_CASE(8) NSGA3_CASE(9) NSGA3_CASE(10) NSGA3_CASE(11) NSGA3_CASE(12) NSGA3_CASE(13)
+        NSGA3_CASE(14) NSGA3_CASE(15) NSGA3_CASE(16)
+#undef NSGA3_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t run_bit_counts(const SortViews &v, hipStream_t s) {
     switch (v.M) {
 #define NSGA3_CASE(m) case m: return launch_counts<m>(v, s);

@@ -77,6 +77,8 @@ hipError_t run_sort_stage(const SortViews &v, const LaunchCfg &cfg, hipStream_t 
 
 // ---- bitdom.hip -----------------------------------------------------------
 hipError_t run_bit_counts(const SortViews &v, hipStream_t s);
+// Block tables of all sorted points (tabs_all), as the count stage builds them.
+hipError_t run_build_all_tables(const SortViews &v, hipStream_t s);
 void run_bit_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk, const int32_t *urun,
                    int32_t *ucnt, int level, unsigned grid, hipStream_t s);
 size_t bit_tables_bytes(int64_t N, int M);
@@ -86,6 +88,31 @@ hipError_t run_peel(const SortViews &v, const LaunchCfg &cfg, hipStream_t s);
 // Largest cooperative grid the peeling tail may use for this M (0 on error).
 int peel_max_blocks_per_cu(int M);
 size_t split_state_entries(int64_t N);
+
+// ---- hype.hip -------------------------------------------------------------
+// TensorHypE selection after the sort stage (ranks and the last front of n).
+struct HypeViews {
+    const float *objs;
+    int64_t N;
+    int M;
+    int64_t n;                   // population size to keep
+    const float *vref;           // [M] reference point (device)
+    const float *U;              // [s * M] uniform draws (device)
+    int64_t s;
+    int32_t *selected;           // [n] ascending
+    double *d;                   // [N] or null: HV estimate on rank <= l, -inf elsewhere
+    const int32_t *rank;         // [N] original order (from the sort stage)
+    const uint32_t *tabs_all;    // block tables of all points (sorted order)
+    uint64_t *skey, *skey_alt;   // [N] sort keys (the presort's buffers, free by now)
+    uint32_t *sval, *sval_alt;
+    uint32_t *temp;              // radix-sort / scan scratch
+    uint8_t *selflag;            // [N]
+    DevScalars *sc;
+    nsga3_info *info;
+    void *extra;                 // hype_extra_bytes(N, M, s)
+};
+size_t hype_extra_bytes(int64_t N, int M, int64_t s);
+hipError_t run_hype(const HypeViews &v, hipStream_t st);
 
 // ---- rvea.hip -------------------------------------------------------------
 // TensorRVEA angle-penalized distance selection (one elite per reference).
@@ -107,6 +134,8 @@ hipError_t run_rvea(const RveaViews &v, hipStream_t s);
 
 // ---- select.hip -----------------------------------------------------------
 size_t oneshot_temp_bytes(int64_t n);   // workspace temp needed by the one-shot niching
+// nsga3_info from the call's device scalars (K selections expected).
+void run_finalize(nsga3_info *info, int64_t K, const DevScalars *sc, hipStream_t s);
 struct SelectViews {
     const float *objs;
     int64_t N;

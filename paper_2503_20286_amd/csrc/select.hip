@@ -752,6 +752,10 @@ size_t oneshot_temp_bytes(int64_t n) {
     return (size_t)(2 * (nb + 64) + 64) * sizeof(uint32_t);
 }
 
+void run_finalize(nsga3_info *info, int64_t K, const DevScalars *sc, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, info, K, sc);
+}
+
 int normalize_partial_blocks(int64_t N) {
     int64_t nb = (N + kNormThreads - 1) / kNormThreads;
     if (nb > kNormBlocksMax) nb = kNormBlocksMax;
