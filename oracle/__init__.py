@@ -47,6 +47,10 @@ def _declare(L):
     L.oracle_select.argtypes = [P, i64, i32, P, i32, i64, P, P, P, P, P, P, P]
     L.oracle_select_mode.argtypes = [P, i64, i32, P, i32, i64, i32, P, P, P, P, P, P, P]
     L.oracle_num_threads.argtypes = []
+    L.oracle_sbx_pm.argtypes = [P, i64, i32, P, P, ctypes.c_double, ctypes.c_double, P, P, P]
+    L.oracle_sbx_pm.restype = ctypes.c_int
+    L.oracle_gather_rows.argtypes = [P, i64, i32, P, i64, P]
+    L.oracle_gather_rows.restype = ctypes.c_int
     L.oracle_hype_alpha.argtypes = [i64, i64, P]
     L.oracle_hype_alpha.restype = ctypes.c_int
     L.oracle_hype_hv.argtypes = [P, i64, i32, P, P, i64, i64, P, P]
@@ -334,3 +338,32 @@ def hype_select(objs, vref, U, n):
     _check(lib().oracle_hype_select(_ptr(f), N, M, _ptr(v), _ptr(u), u.shape[0], int(n), _ptr(sel),
                                     _ptr(d), _ptr(rank), _ptr(info)), "oracle_hype_select")
     return HypeSelection(sel, d, rank, *[int(x) for x in info])
+
+
+# ---------------------------------------------------------------------------
+# Variation (Supplementary Sec. S.I: SBX and polynomial mutation) and the
+# gather of the selected rows (Eq. (13))
+# ---------------------------------------------------------------------------
+def sbx_pm(X, lower, upper, eta_c, eta_m, r_sbx, r_pm):
+    """float64[2h, d] offspring: SBX children of rows r and h + r, clipped,
+    then polynomially mutated (every variable)."""
+    x = np.ascontiguousarray(X, dtype=np.float32)
+    n, d = x.shape
+    h = n // 2
+    lo = np.ascontiguousarray(lower, dtype=np.float32)
+    hi = np.ascontiguousarray(upper, dtype=np.float32)
+    rs = np.ascontiguousarray(r_sbx, dtype=np.float32)
+    rp = np.ascontiguousarray(r_pm, dtype=np.float32)
+    out = np.zeros((2 * h, d), np.float64)
+    _check(lib().oracle_sbx_pm(_ptr(x), n, d, _ptr(lo), _ptr(hi), float(eta_c), float(eta_m),
+                               _ptr(rs), _ptr(rp), _ptr(out)), "oracle_sbx_pm")
+    return out
+
+
+def gather_rows(X, idx):
+    x = np.ascontiguousarray(X, dtype=np.float32)
+    i = np.ascontiguousarray(idx, dtype=np.int32)
+    out = np.zeros((i.size, x.shape[1]), np.float32)
+    _check(lib().oracle_gather_rows(_ptr(x), x.shape[0], x.shape[1], _ptr(i), i.size, _ptr(out)),
+           "oracle_gather_rows")
+    return out

@@ -5,7 +5,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, f) for f in ("oracle.c", "rvea.c", "hype.c")]
+SRCS = [os.path.join(HERE, f) for f in ("oracle.c", "rvea.c", "hype.c", "variation.c")]
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 
