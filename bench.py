@@ -58,6 +58,8 @@ def parse():
                     help="skip the TensorRVEA selection report")
     ap.add_argument("--no-hype", action="store_true",
                     help="skip the TensorHypE selection report")
+    ap.add_argument("--no-variation", action="store_true",
+                    help="skip the SBX / polynomial mutation and gather report")
     ap.add_argument("--assoc", default="fp32", choices=["fp32", "bf16"],
                     help="association screening precision (re-scoring is float64 in both)")
     ap.add_argument("--no-batch", action="store_true",
@@ -316,6 +318,48 @@ def hype_report(args):
         ctx.close()
         out[name] = rec
     return out
+
+
+def variation_report(args):
+    """SBX and polynomial mutation (Supplementary Sec. S.I) of a population of
+    n = 10,000 with d = 4,096 variables (the decision-space size of the
+    paper's largest robot-control problems), and the gather of 10,000 rows:
+    HBM rooflines (algorithmic bytes: every input read once, every output
+    written once)."""
+    import torch
+
+    import paper_2503_20286_amd as nsga3
+    n, d = 10_000, 4096
+    h = n // 2
+    g = torch.Generator(device="cuda").manual_seed(7)
+    X = torch.rand((n, d), device="cuda", generator=g)
+    lo = torch.zeros(d, device="cuda")
+    hi = torch.ones(d, device="cuda")
+    rs = torch.rand((h, d), device="cuda", generator=g)
+    rp = torch.rand((2 * h, d), device="cuda", generator=g)
+    out = torch.empty((2 * h, d), device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        nsga3.sbx_pm(X, lo, hi, 20.0, 20.0, rs, rp, out=out, status=st)
+    ms = _time_calls(lambda: nsga3.sbx_pm(X, lo, hi, 20.0, 20.0, rs, rp, out=out, status=st),
+                     args.steps, torch.cuda.current_stream())
+    var_bytes = 4.0 * (2 * h * d + h * d + 2 * h * d + 2 * h * d + 2 * d)
+    idx = torch.randperm(2 * h, device="cuda", generator=g)[:h].to(torch.int32).contiguous()
+    rows = torch.empty((h, d), device="cuda")
+    for _ in range(args.warmup):
+        nsga3.gather_rows(out, idx, out=rows, status=st)
+    ms_g = _time_calls(lambda: nsga3.gather_rows(out, idx, out=rows, status=st), args.steps,
+                       torch.cuda.current_stream())
+    g_bytes = 4.0 * (2 * h * d + h)     # h rows read and written, indices read
+    torch.cuda.synchronize()
+    return {
+        "workload": f"n={n} d={d}",
+        "sbx_pm": {"ms": ms, "bytes": var_bytes, "achieved_GB_s": var_bytes / (ms / 1e3) / 1e9,
+                   "frac_of_hbm_peak": var_bytes / (ms / 1e3) / 8e12, "status": int(st.item())},
+        "gather": {"rows": h, "ms": ms_g, "bytes": g_bytes,
+                   "achieved_GB_s": g_bytes / (ms_g / 1e3) / 1e9,
+                   "frac_of_hbm_peak": g_bytes / (ms_g / 1e3) / 8e12},
+    }
 
 
 def c5_report(args):
@@ -595,6 +639,8 @@ def main():
         res["rvea"] = rvea_report(args, w, objs, refs)
     if not args.no_hype and args.workload == "large":
         res["hype"] = hype_report(args)
+    if not args.no_variation and args.workload == "large":
+        res["variation"] = variation_report(args)
     if not args.no_c5 and args.workload == "large":
         res["c5"] = c5_report(args)
     print(json.dumps(res), flush=True)

@@ -148,6 +148,42 @@ nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t 
                           hipStream_t stream);
 
 /*
+ * Variation around the selection (Supplementary Sec. S.I): simulated binary
+ * crossover (Eq. (S.6)-(S.7)) of rows r and h + r of the n x d population X
+ * (h = floor(n / 2); children at rows r and h + r of `offspring`), the children
+ * clipped to [lower, upper], then polynomial mutation (Eq. (S.8)-(S.11)) of
+ * every variable of both children.  With a draw m per (row, variable):
+ *   B = (2m)^(1/(eta_c+1)) for m <= 1/2, else (1/(2 - 2m))^(1/(eta_c+1));
+ *   children ((1 +- B) x1 + (1 -+ B) x2) / 2;
+ *   mutation step (eta = eta_m + 1, D = u - l, d1 = (x - l)/D, d2 = (u - x)/D):
+ *   (2m + (1 - 2m)(1 - d1)^eta)^(1/eta) - 1 for m <= 1/2, else
+ *   1 - (2 - 2m + (2m - 1)(1 - d2)^eta)^(1/eta); x' = x + step D.
+ *
+ *   X          DEVICE float[n*d]   population, row-major (n >= 2; an odd last row is unused)
+ *   lower, upper DEVICE float[d]   bounds, finite, lower < upper
+ *   eta_c, eta_m                   distribution indices (finite, >= 0)
+ *   r_sbx      DEVICE float[h*d]   the caller's uniform draws in [0, 1) for the crossover
+ *   r_pm       DEVICE float[2h*d]  ... and for the mutation of every child variable
+ *   offspring  DEVICE float[2h*d]  output
+ *   status     DEVICE int32*       optional: NSGA3_OK, or NSGA3_E_NONFINITE (bad bounds or a
+ *                                  non-finite result)
+ * Float32 arithmetic (powers through the hardware base-2 logarithm and
+ * exponential).  Needs no context and allocates nothing.  Asynchronous.
+ */
+nsga3_status nsga3_sbx_pm(const float *X, int64_t n, int32_t d, const float *lower,
+                          const float *upper, double eta_c, double eta_m, const float *r_sbx,
+                          const float *r_pm, float *offspring, int32_t *status, hipStream_t stream);
+
+/*
+ * Gather of the selected rows (Eq. (13)): out row q = X row idx[q].
+ *   X DEVICE float[N*d], idx DEVICE int32[K], out DEVICE float[K*d];
+ *   status DEVICE int32* optional: NSGA3_E_INVALID if an index lies outside
+ *   [0, N) (that row is not written).  Needs no context.  Asynchronous.
+ */
+nsga3_status nsga3_gather_rows(const float *X, int64_t N, int32_t d, const int32_t *idx, int64_t K,
+                               float *out, int32_t *status, hipStream_t stream);
+
+/*
  * Environmental selection of TensorHypE (Sec. IV-C; Supplementary Alg. S.10,
  * S.11): the nondominated sort of nsga3_select gives ranks r and the last
  * admitted front l for a population of n; every point of r < l is kept, and

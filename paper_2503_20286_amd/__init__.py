@@ -15,8 +15,8 @@ from ._native import (  # noqa: F401
     ASSOC_BF16, ASSOC_FP32, NICHING_EXACT, NICHING_ONESHOT, NUM_PHASES, PHASES, Context, Info,
     NativeError, Plan, Selection, STATUS, default_context, exported_symbols, header_symbols, lib_path, load, select, version,
     workspace_size, select_noalloc, alloc_outputs, rvea_select, RveaSelection,
-    hype_select, HypeSelection,
+    hype_select, HypeSelection, sbx_pm, gather_rows,
 )
 
 __all__ = ["select", "Context", "Plan", "Selection", "Info", "NativeError", "load", "version",
-           "ASSOC_FP32", "ASSOC_BF16", "NICHING_EXACT", "NICHING_ONESHOT", "rvea_select", "hype_select"]
+           "ASSOC_FP32", "ASSOC_BF16", "NICHING_EXACT", "NICHING_ONESHOT", "rvea_select", "hype_select", "sbx_pm", "gather_rows"]

@@ -94,6 +94,10 @@ def load():
                                         P, P]
         L.nsga3_hype_select.argtypes = [P, P, i64, i32, P, P, i64, i64, P, P, P, P, P]
         L.nsga3_hype_select.restype = ctypes.c_int
+        L.nsga3_sbx_pm.argtypes = [P, i64, i32, P, P, ctypes.c_double, ctypes.c_double, P, P, P, P, P]
+        L.nsga3_sbx_pm.restype = ctypes.c_int
+        L.nsga3_gather_rows.argtypes = [P, i64, i32, P, i64, P, P, P]
+        L.nsga3_gather_rows.restype = ctypes.c_int
         L.nsga3_rvea_select.restype = ctypes.c_int
         L.nsga3_status_string.argtypes = [ctypes.c_int]
         L.nsga3_status_string.restype = ctypes.c_char_p
@@ -428,6 +432,61 @@ def hype_select(objs, vref, U, n: int, *, ctx: Optional[Context] = None,
     if rc != 0:
         raise NativeError("nsga3_hype_select", rc, ctx._lib)
     return out
+
+
+def sbx_pm(X, lower, upper, eta_c: float, eta_m: float, r_sbx, r_pm, *, out=None, status=None,
+           stream=None):
+    """Simulated binary crossover and polynomial mutation (nsga3_sbx_pm):
+    offspring of the n x d population X from the caller's uniform draws
+    (r_sbx: h x d, r_pm: 2h x d, h = n // 2).  Returns (offspring, status)."""
+    import torch
+    for t_, nm in ((X, "X"), (r_sbx, "r_sbx"), (r_pm, "r_pm")):
+        _check_tensor(t_, nm, 2)
+    _check_tensor(lower, "lower", 1)
+    _check_tensor(upper, "upper", 1)
+    n, d = X.shape
+    h = n // 2
+    if tuple(r_sbx.shape) != (h, d) or tuple(r_pm.shape) != (2 * h, d):
+        raise ValueError("r_sbx must be (n//2, d) and r_pm (2*(n//2), d)")
+    if lower.shape[0] != d or upper.shape[0] != d:
+        raise ValueError("bounds must have d entries")
+    dev = X.device
+    if out is None:
+        out = torch.empty((2 * h, d), dtype=torch.float32, device=dev)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    L = load()
+    rc = L.nsga3_sbx_pm(ctypes.c_void_p(X.data_ptr()), int(n), int(d), ctypes.c_void_p(lower.data_ptr()),
+                        ctypes.c_void_p(upper.data_ptr()), float(eta_c), float(eta_m),
+                        ctypes.c_void_p(r_sbx.data_ptr()), ctypes.c_void_p(r_pm.data_ptr()),
+                        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+                        ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise NativeError("nsga3_sbx_pm", rc, L)
+    return out, status
+
+
+def gather_rows(X, idx, *, out=None, status=None, stream=None):
+    """Rows idx of X (nsga3_gather_rows, Eq. (13)).  Returns (rows, status)."""
+    import torch
+    _check_tensor(X, "X", 2)
+    if idx.dtype != torch.int32 or idx.device != X.device or not idx.is_contiguous():
+        raise ValueError("idx must be a contiguous int32 tensor on X's device")
+    N, d = X.shape
+    K = idx.shape[0]
+    if out is None:
+        out = torch.empty((K, d), dtype=torch.float32, device=X.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=X.device)
+    s = stream if stream is not None else torch.cuda.current_stream(X.device)
+    L = load()
+    rc = L.nsga3_gather_rows(ctypes.c_void_p(X.data_ptr()), int(N), int(d),
+                             ctypes.c_void_p(idx.data_ptr()), int(K), ctypes.c_void_p(out.data_ptr()),
+                             ctypes.c_void_p(status.data_ptr()), ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise NativeError("nsga3_gather_rows", rc, L)
+    return out, status
 
 
 def alloc_outputs(N: int, K: int, device, want_counts: bool = True,

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libnsga3.so")
 SOURCES = ["api.hip", "bitdom.hip", "dominance.hip", "engine.hip", "hype.hip", "peel.hip",
-           "rvea.hip", "select.hip", "sort_scan.hip"]
+           "rvea.hip", "select.hip", "sort_scan.hip", "variation.hip"]
 ARCH = "gfx950"
 
 

@@ -630,6 +630,31 @@ nsga3_status nsga3_select_noalloc(const float *objs, int64_t N, int32_t M, const
     return enqueue_select(a, p, stream) == hipSuccess ? NSGA3_OK : NSGA3_E_HIP;
 }
 
+nsga3_status nsga3_sbx_pm(const float *X, int64_t n, int32_t d, const float *lower,
+                          const float *upper, double eta_c, double eta_m, const float *r_sbx,
+                          const float *r_pm, float *offspring, int32_t *status, hipStream_t stream) {
+    if (!X || !lower || !upper || !r_sbx || !r_pm || !offspring) return NSGA3_E_INVALID;
+    if (n < 2 || n > 2147483647LL || d < 1 || !(eta_c >= 0.0) || !(eta_m >= 0.0) || !isfinite(eta_c) ||
+        !isfinite(eta_m))
+        return NSGA3_E_INVALID;
+    if (run_sbx_pm(X, n, d, lower, upper, eta_c, eta_m, r_sbx, r_pm, offspring, status, stream) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return NSGA3_E_HIP;
+    }
+    return NSGA3_OK;
+}
+
+nsga3_status nsga3_gather_rows(const float *X, int64_t N, int32_t d, const int32_t *idx, int64_t K,
+                               float *out, int32_t *status, hipStream_t stream) {
+    if (!X || !idx || !out || N < 1 || N > 2147483647LL || d < 1 || K < 1) return NSGA3_E_INVALID;
+    if (run_gather(X, N, d, idx, K, out, status, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return NSGA3_E_HIP;
+    }
+    return NSGA3_OK;
+}
+
 nsga3_status nsga3_hype_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t M,
                                const float *vref, const float *U, int64_t s, int64_t n,
                                int32_t *selected, double *d, int32_t *rank, nsga3_info *info,

@@ -89,6 +89,13 @@ hipError_t run_peel(const SortViews &v, const LaunchCfg &cfg, hipStream_t s);
 int peel_max_blocks_per_cu(int M);
 size_t split_state_entries(int64_t N);
 
+// ---- variation.hip --------------------------------------------------------
+hipError_t run_sbx_pm(const float *X, int64_t n, int d, const float *lower, const float *upper,
+                      double eta_c, double eta_m, const float *r_sbx, const float *r_pm, float *out,
+                      int32_t *status, hipStream_t s);
+hipError_t run_gather(const float *X, int64_t N, int d, const int32_t *idx, int64_t K, float *out,
+                      int32_t *status, hipStream_t s);
+
 // ---- hype.hip -------------------------------------------------------------
 // TensorHypE selection after the sort stage (ranks and the last front of n).
 struct HypeViews {
