@@ -78,40 +78,58 @@ __global__ __launch_bounds__(kThreads) void k_split(
     }
     uint32_t tot;
     const uint32_t ex = block_exclusive_scan((zf << 16) | zu, lds, &tot);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < kWave) {
+        // look-back by the first wave: lane q reads the state of block
+        // base - q, so one round covers 64 predecessors; the nearest block
+        // with an inclusive prefix ends the walk (before block 0 the prefix
+        // is 0), and every block nearer than it must have published its
+        // aggregate, or the round is read again
         const uint32_t bf = tot >> 16, bu = tot & 0xffffu;
+        const int lane = (int)lane_id();
         uint32_t pf = 0, pu = 0;
         if (blockIdx.x == 0) {
-            __hip_atomic_store(&lb_cur[0], lb_pack(2, bf, bu), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(&lb_cur[0], lb_pack(2, bf, bu), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            __hip_atomic_store(&lb_cur[blockIdx.x], lb_pack(1, bf, bu), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            int32_t q = (int32_t)blockIdx.x - 1;
+            if (lane == 0)
+                __hip_atomic_store(&lb_cur[blockIdx.x], lb_pack(1, bf, bu), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            int32_t base = (int32_t)blockIdx.x - 1;
             uint64_t spins = 0;
-            while (q >= 0) {
-                const uint64_t v = __hip_atomic_load(&lb_cur[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while (true) {
+                const int32_t q = base - lane;
+                const uint64_t v = q >= 0 ? __hip_atomic_load(&lb_cur[q], __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT)
+                                          : lb_pack(2, 0, 0);
                 const uint32_t st = (uint32_t)(v >> 62);
-                if (st == 0) {
+                const uint64_t inc = ballot(st == 2);
+                const int first = inc ? __builtin_ctzll(inc) : kWave;   // nearest inclusive lane
+                const uint64_t need = first < kWave - 1 ? ((2ull << first) - 1ull) : ~0ull;
+                if (ballot(st == 0) & need) {
                     __builtin_amdgcn_s_sleep(1);
                     if (++spins > (1ull << 26)) {  // a predecessor never published
-                        atomicOr(&sc->err, (uint32_t)kErrBarrierTimeout);
+                        if (lane == 0) atomicOr(&sc->err, (uint32_t)kErrBarrierTimeout);
                         break;
                     }
                     continue;
                 }
-                pf += (uint32_t)(v >> 31) & 0x7fffffffu;
-                pu += (uint32_t)v & 0x7fffffffu;
-                if (st == 2) break;
-                --q;
+                const bool take = lane <= first;
+                pf += wave_sum(take ? (uint32_t)(v >> 31) & 0x7fffffffu : 0u);
+                pu += wave_sum(take ? (uint32_t)v & 0x7fffffffu : 0u);
+                if (inc) break;
+                base -= kWave;
             }
-            __hip_atomic_store(&lb_cur[blockIdx.x], lb_pack(2, pf + bf, pu + bu), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(&lb_cur[blockIdx.x], lb_pack(2, pf + bf, pu + bu), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_pref[0] = pf;
-        s_pref[1] = pu;
-        if ((int32_t)blockIdx.x == nb - 1) {
-            fsize[level] = (int32_t)(pf + bf);
-            usize[level] = (int32_t)(pu + bu);
+        if (lane == 0) {
+            s_pref[0] = pf;
+            s_pref[1] = pu;
+            if ((int32_t)blockIdx.x == nb - 1) {
+                fsize[level] = (int32_t)(pf + bf);
+                usize[level] = (int32_t)(pu + bu);
+            }
         }
     }
     __syncthreads();
