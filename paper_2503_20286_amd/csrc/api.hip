@@ -60,7 +60,8 @@ struct nsga3_ctx {
     bool tail_block;
     int out_mode;                   // NSGA3_SEPARATE_OUT: LaunchCfg::out_mode
     int fixed_levels;               // > 0: always enqueue this many peeling levels
-    volatile int32_t *last_fronts;  // pinned: front count of the latest call
+    double tail_work;               // peeling work left for the one-work-group tail
+    volatile int32_t *last_fronts;  // pinned: front count, then level sizes, of the latest call
     std::vector<hipEvent_t> ev_pool;   // NSGA3_NUM_PHASES + 1 events per recorded call
     size_t ev_used;
 };
@@ -210,7 +211,14 @@ struct PhaseMarks {
 };
 
 
-LaunchCfg ctx_cfg(const nsga3_ctx *ctx, int M) {
+// Peeling work (front size x points left, summed over the levels from the
+// tail's first level on) at or below which the last levels go to one
+// work-group instead of three launches each.  One work-group has a
+// thousandth of the chip's lanes, so only nearly empty levels belong there
+// (N = 200k, M = 5: peel 1.15 ms at 1e4 or 3e4, 1.21 at 1e5, 1.42 at 4e5).
+constexpr double kTailPairWork = 1.0e4;
+
+LaunchCfg ctx_cfg(const nsga3_ctx *ctx, int M, int64_t N) {
     LaunchCfg cfg;
     cfg.num_cus = ctx->num_cus;
     cfg.peel_blocks_per_cu = ctx->peel_bpc[M];
@@ -218,11 +226,34 @@ LaunchCfg ctx_cfg(const nsga3_ctx *ctx, int M) {
     cfg.bitsets = ctx->bitsets;
     cfg.tail_block = ctx->tail_block;
     cfg.out_mode = ctx->out_mode;
-    // enqueue one more level than the previous call needed (its front count
-    // arrives asynchronously in pinned memory; a stale value only shifts work
-    // between the enqueued levels and the tail)
-    const int prev = ctx->last_fronts ? *ctx->last_fronts : 0;
+    // The previous call's front count and level sizes arrive asynchronously
+    // in pinned memory; they only size launches (a stale or torn read shifts
+    // work between the enqueued levels and the tail, never the results).
+    // Enqueue one level more than the previous call needed, or stop where the
+    // work left is small enough for one work-group.
+    const volatile int32_t *fb = ctx->last_fronts;
+    const int prev = fb ? fb[0] : 0;
     int lv = prev > 0 ? prev + 1 : kDefaultHostLevels;
+    if (prev > 0 && prev <= kProfLevels && fb[1 + prev - 1] == 0) {
+        int32_t u[kProfLevels];
+        bool ok = true;
+        for (int k = 0; k < prev; ++k) {
+            u[k] = fb[1 + k];
+            const int64_t before = k ? u[k - 1] : N;
+            if (u[k] < 0 || u[k] > before) ok = false;
+        }
+        if (ok) {
+            for (int k = 0; k < prev; ++k) cfg.fprev[k] = (int32_t)((k ? u[k - 1] : N) - u[k]);
+            double work = 0.0;
+            int k0 = prev;
+            for (int k = prev - 1; k >= 1; --k) {
+                work += (double)cfg.fprev[k] * (double)u[k];
+                if (work > ctx->tail_work || u[k - 1] > kTailOneBlockMax) break;
+                k0 = k;
+            }
+            if (k0 < prev) lv = k0;
+        }
+    }
     if (ctx->fixed_levels > 0) lv = ctx->fixed_levels;
     if (lv > kMaxHostLevels) lv = kMaxHostLevels;
     if (lv < 1) lv = 1;
@@ -236,7 +267,7 @@ struct EnqArgs {
     int assoc;
     int niching = NSGA3_NICHING_EXACT;
     nsga3_ctx *marks;                 // record phase events into this context, or null
-    volatile int32_t *last_fronts;    // pinned slot for the front count, or null
+    volatile int32_t *last_fronts;    // pinned slot for the front count and level sizes, or null
 };
 
 // Views of the sort stage (a0-a3) over the workspace w carved by L.
@@ -299,7 +330,6 @@ hipError_t enqueue_select(const EnqArgs &a, const nsga3_problem &p, hipStream_t 
     const int32_t M = p.M, H = p.H;
     int32_t *selected = p.selected, *rank = p.rank, *niche = p.niche;
     float *dist = p.dist;
-    int32_t *dom_in = p.dom_in, *dom_out = p.dom_out;
     nsga3_info *info = p.info;
     const Layout L = layout_for(N, M, H, kGridCap);
     char *w = a.ws;
@@ -327,7 +357,7 @@ hipError_t enqueue_select(const EnqArgs &a, const nsga3_problem &p, hipStream_t 
     const LaunchCfg &cfg = a.cfg;
     if (e == hipSuccess) e = run_sort_stage(sv, cfg, stream);
     if (e == hipSuccess && a.last_fronts)
-        e = hipMemcpyAsync((void *)a.last_fronts, &sc->num_fronts, sizeof(int32_t),
+        e = hipMemcpyAsync((void *)a.last_fronts, &sc->fb[0], sizeof(int32_t) * (1 + kProfLevels),
                            hipMemcpyDeviceToHost, stream);
 
     SelectViews xv;
@@ -512,6 +542,10 @@ nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt)
     // by the objective count
     c->out_mode = -1;
     if (const char *e = getenv("NSGA3_SEPARATE_OUT")) c->out_mode = atoi(e) != 0 ? 1 : 0;
+    // NSGA3_TAIL_WORK: pair tests (front size x points left, summed over the
+    // last levels) at or below which those levels go to one work-group
+    c->tail_work = kTailPairWork;
+    if (const char *e = getenv("NSGA3_TAIL_WORK")) c->tail_work = atof(e);
     if (const char *e = getenv("NSGA3_HOST_LEVELS")) {
         const int v = atoi(e);
         if (v >= 1 && v <= kMaxHostLevels) c->fixed_levels = v;
@@ -523,7 +557,7 @@ nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt)
     c->last_fronts = nullptr;
     {
         void *h = nullptr;
-        if (hipHostMalloc(&h, 64, hipHostMallocDefault) == hipSuccess) {
+        if (hipHostMalloc(&h, sizeof(int32_t) * (1 + kProfLevels), hipHostMallocDefault) == hipSuccess) {
             c->last_fronts = (volatile int32_t *)h;
             *c->last_fronts = 0;
         } else {
@@ -590,7 +624,7 @@ nsga3_status nsga3_select(nsga3_ctx *ctx, const float *objs, int64_t N, int32_t 
     if (st != NSGA3_OK) return st;
     EnqArgs a;
     a.ws = (char *)ctx->ws;
-    a.cfg = ctx_cfg(ctx, M);
+    a.cfg = ctx_cfg(ctx, M, N);
     a.assoc = (int)ctx->opt.assoc;
     a.niching = (int)ctx->opt.niching;
     a.marks = ctx->profiling ? ctx : nullptr;
@@ -670,7 +704,7 @@ nsga3_status nsga3_hype_select(nsga3_ctx *ctx, const float *objs, int64_t N, int
 #define WS(T, f) reinterpret_cast<T *>(w + L.f)
     DevScalars *sc = WS(DevScalars, sc);
     int32_t *rank_o = rank ? rank : WS(int32_t, rank);
-    const LaunchCfg cfg = ctx_cfg(ctx, M);
+    const LaunchCfg cfg = ctx_cfg(ctx, M, N);
     PhaseMarks marks(nullptr, stream);   // phase timing covers nsga3_select only
     Marker mk;
     mk.fn = [](void *x) { static_cast<PhaseMarks *>(x)->mark(); };
@@ -686,7 +720,7 @@ nsga3_status nsga3_hype_select(nsga3_ctx *ctx, const float *objs, int64_t N, int
     SortViews sv = sort_views(w, L, p, rank_o, mk, cfg);
     if (e == hipSuccess) e = run_sort_stage(sv, cfg, stream);
     if (e == hipSuccess && ctx->last_fronts)
-        e = hipMemcpyAsync((void *)ctx->last_fronts, &sc->num_fronts, sizeof(int32_t),
+        e = hipMemcpyAsync((void *)ctx->last_fronts, &sc->fb[0], sizeof(int32_t) * (1 + kProfLevels),
                            hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess && !cfg.bitsets) e = run_build_all_tables(sv, stream);
     if (e == hipSuccess) {
@@ -1220,9 +1254,10 @@ nsga3_status nsga3_plan_create(nsga3_ctx *ctx, const nsga3_problem *probs, int32
                 if (e != hipSuccess) break;
                 EnqArgs a;
                 a.ws = (char *)pl->ws[q];
-                a.cfg = ctx_cfg(ctx, probs[b].M);
+                a.cfg = ctx_cfg(ctx, probs[b].M, probs[b].N);
                 a.cfg.tail_block = true;       // cooperative launches cannot be captured
                 a.cfg.host_levels = levels;
+                for (int k = 0; k < kProfLevels; ++k) a.cfg.fprev[k] = 0;  // replays see other data
                 a.assoc = (int)ctx->opt.assoc;
                 a.niching = (int)ctx->opt.niching;
                 a.marks = nullptr;

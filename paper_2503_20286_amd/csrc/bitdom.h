@@ -186,13 +186,10 @@ __device__ __forceinline__ void build_block(const uint32_t *__restrict__ rec, in
         inv[rank] = l;
         block_sync<kWaveSync>();
         const int mem = inv[l];
-        uint64_t bit = (mem < nmem) ? (1ull << mem) : 0ull;
-        for (int o = 1; o < kBlk; o <<= 1) {
-            const uint64_t t = __shfl_up(bit, o, 64);
-            if (l >= o) bit |= t;
-        }
-        T[blk_mask_lo(k, l + 1)] = (uint32_t)bit;
-        T[blk_mask_hi(k, l + 1)] = (uint32_t)(bit >> 32);
+        const uint64_t bit = (mem < nmem) ? (1ull << mem) : 0ull;
+        // prefix masks: members of ranks 0..l
+        T[blk_mask_lo(k, l + 1)] = wave_inclusive_scan<true>((uint32_t)bit);
+        T[blk_mask_hi(k, l + 1)] = wave_inclusive_scan<true>((uint32_t)(bit >> 32));
         if (l == 0) {
             T[blk_mask_lo(k, 0)] = 0u;
             T[blk_mask_hi(k, 0)] = 0u;

@@ -16,20 +16,20 @@
 namespace nsga3 {
 
 // Block tables of a list of n records (n_static, or *n_dev when n_static < 0):
-// one table per work-group, its objectives spread over the waves (a table's
-// latency is that of ceil(M / kBuildWaves) objectives, which matters for the
-// small fronts of late peeling levels).
-constexpr int kBuildWaves = 4;
-
+// one table per work-group at a time, one wave per objective (a table's
+// latency is that of one objective, which matters for the small fronts of
+// late peeling levels).
 template <int M>
-__global__ __launch_bounds__(kBuildWaves * kWave) void k_build_blocks(
+__global__ __launch_bounds__(M * kWave) void k_build_blocks(
     const uint32_t *__restrict__ rec, int32_t n_static, const int32_t *__restrict__ n_dev,
     uint32_t *__restrict__ tabs, const DevScalars *__restrict__ sc) {
-    __shared__ int32_t inv[kBuildWaves][kBlk];
+    __shared__ int32_t inv[M][kBlk];
     if (sc->err) return;
     const int32_t n = n_static >= 0 ? n_static : *n_dev;
+    const int32_t nblk = (n + kBlk - 1) / kBlk;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    build_block<M, true>(rec, n, tabs, (int32_t)blockIdx.x, inv[w], w, kBuildWaves);
+    for (int32_t b = (int32_t)blockIdx.x; b < nblk; b += (int32_t)gridDim.x)
+        build_block<M, true>(rec, n, tabs, b, inv[w], w, M);
 }
 
 inline unsigned build_grid(int64_t nblk) { return (unsigned)nblk; }
@@ -439,7 +439,7 @@ static hipError_t launch_counts(const SortViews &v, hipStream_t s) {
     const int32_t N = (int32_t)v.N;
     const int32_t nblk = (N + kBlk - 1) / kBlk;
     constexpr int CB = count_chunk<M>();
-    hipLaunchKernelGGL(k_build_blocks<M>, dim3(build_grid(nblk)), dim3(kBuildWaves * kWave), 0, s, v.recs, N,
+    hipLaunchKernelGGL(k_build_blocks<M>, dim3(build_grid(nblk)), dim3(M * kWave), 0, s, v.recs, N,
                        (const int32_t *)nullptr, v.tabs_all, v.sc);
     const unsigned nIC = (unsigned)((nblk + CB - 1) / CB);
     const unsigned nJT = (unsigned)((N + kTileJ - 1) / kTileJ);
@@ -464,7 +464,7 @@ template <int M>
 static hipError_t launch_build_all(const SortViews &v, hipStream_t s) {
     const int32_t N = (int32_t)v.N;
     const int32_t nblk = (N + kBlk - 1) / kBlk;
-    hipLaunchKernelGGL(k_build_blocks<M>, dim3(build_grid(nblk)), dim3(kBuildWaves * kWave), 0, s, v.recs,
+    hipLaunchKernelGGL(k_build_blocks<M>, dim3(build_grid(nblk)), dim3(M * kWave), 0, s, v.recs,
                        N, (const int32_t *)nullptr, v.tabs_all, v.sc);
     return hipGetLastError();
 }
@@ -493,19 +493,24 @@ hipError_t run_bit_counts(const SortViews &v, hipStream_t s) {
 
 template <int M>
 static void launch_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk,
-                         const int32_t *urun, int32_t *ucnt, int level, unsigned grid, hipStream_t s) {
+                         const int32_t *urun, int32_t *ucnt, int level, unsigned grid,
+                         int32_t f_expect, hipStream_t s) {
     const int32_t N = (int32_t)v.N;
     const int32_t nblk_max = (N + kBlk - 1) / kBlk;
-    hipLaunchKernelGGL(k_build_blocks<M>, dim3(build_grid(nblk_max)), dim3(kBuildWaves * kWave), 0, s, fk, -1,
+    // the front's size is on the device: size the build grid from the size
+    // expected (the kernel strides over any larger front), else for every point
+    int32_t bgrid = nblk_max;
+    if (f_expect > 0) bgrid = min(nblk_max, (f_expect + kBlk - 1) / kBlk * 5 / 4 + 4);
+    hipLaunchKernelGGL(k_build_blocks<M>, dim3(build_grid(bgrid)), dim3(M * kWave), 0, s, fk, -1,
                        v.fsize + level, v.tabs_lvl, v.sc);
     hipLaunchKernelGGL(k_fwd_level<M>, dim3(grid), dim3(kFwdThreads), 0, s, v.tabs_lvl, uk, urun,
                        ucnt, level, v.fsize, v.usize, v.work, v.sc);
 }
 
 void run_bit_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk, const int32_t *urun,
-                   int32_t *ucnt, int level, unsigned grid, hipStream_t s) {
+                   int32_t *ucnt, int level, unsigned grid, int32_t f_expect, hipStream_t s) {
     switch (v.M) {
-#define NSGA3_CASE(m) case m: launch_level<m>(v, fk, uk, urun, ucnt, level, grid, s); break;
+#define NSGA3_CASE(m) case m: launch_level<m>(v, fk, uk, urun, ucnt, level, grid, f_expect, s); break;
         NSGA3_CASE(2) NSGA3_CASE(3) NSGA3_CASE(4) NSGA3_CASE(5) NSGA3_CASE(6) NSGA3_CASE(7)
         NSGA3_CASE(8) NSGA3_CASE(9) NSGA3_CASE(10) NSGA3_CASE(11) NSGA3_CASE(12) NSGA3_CASE(13)
         NSGA3_CASE(14) NSGA3_CASE(15) NSGA3_CASE(16)

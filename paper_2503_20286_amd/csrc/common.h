@@ -38,6 +38,9 @@ enum : uint32_t {
     kErrBarrierTimeout = 8u,
 };
 
+// Peeling levels whose sizes go back to the host after each call.
+constexpr int kProfLevels = 64;
+
 // Small per-call scalars kept in device memory.
 struct DevScalars {
     uint32_t err;              // kErr* bits
@@ -57,6 +60,7 @@ struct DevScalars {
     uint32_t n_selected;       // number of selection flags set (must equal K)
     double a[16];              // intercepts
     double z[16];              // ideal point (float64 of the float32 minimum)
+    int32_t fb[1 + kProfLevels];  // front count, then points left after each level
 };
 
 // Two-level grid barrier state: blocks arrive on one of kBarSub counters

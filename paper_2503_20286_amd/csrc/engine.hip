@@ -1235,7 +1235,6 @@ __device__ void epi_niche_plan(const EInst &I, EScal *sc, uint32_t *smem) {
 }
 
 __device__ void finalize_info(const EInst &I, EScal *sc) {
-    const ELayout &L = I.L;
     uint32_t e = ld(&sc->err);
     if (e == 0 && (int64_t)ld(&sc->n_selected) != I.K) e |= kErrInternal;
     if (!I.info) return;

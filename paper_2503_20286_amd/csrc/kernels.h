@@ -67,7 +67,15 @@ struct LaunchCfg {
     bool tail_block;            // single-workgroup peeling tail (graph capture)
     int out_mode = -1;          // out-degrees: -1 by objective count, 0 from the in-degree
                                 // pass, 1 by their own backward pass
+    // front sizes per level expected from the previous call (0: unknown);
+    // they size launch grids only, every kernel covers any actual size
+    int32_t fprev[kProfLevels] = {};
 };
+
+// Points left before a peeling tail at or below which one work-group
+// finishes the remaining levels (at most about 2e6 pair tests) instead of the
+// cooperative grid.
+constexpr int kTailOneBlockMax = 2048;
 
 // Whether out-degrees come from the in-degree pass's probes (each dominating
 // member counted in LDS) rather than a backward pass of their own.
@@ -80,7 +88,7 @@ hipError_t run_bit_counts(const SortViews &v, hipStream_t s);
 // Block tables of all sorted points (tabs_all), as the count stage builds them.
 hipError_t run_build_all_tables(const SortViews &v, hipStream_t s);
 void run_bit_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk, const int32_t *urun,
-                   int32_t *ucnt, int level, unsigned grid, hipStream_t s);
+                   int32_t *ucnt, int level, unsigned grid, int32_t f_expect, hipStream_t s);
 size_t bit_tables_bytes(int64_t N, int M);
 
 // ---- peel.hip -------------------------------------------------------------

@@ -20,7 +20,7 @@
 
 namespace nsga3 {
 
-constexpr int kSplitItems = 8;
+constexpr int kSplitItems = 2;
 constexpr int kSplitTile = kThreads * kSplitItems;
 
 // Look-back state word: [63:62] status (0 none, 1 aggregate, 2 inclusive),
@@ -392,68 +392,18 @@ __device__ void tail_phase_a(const uint32_t *__restrict__ fk, int32_t nf,
     }
 }
 
+// One work-group finishes the levels from `level` on (nu points unranked
+// before it), with block barriers only: ordered split, then pairwise
+// decrements of the remaining list by the new front.
 template <int M>
-__global__ __launch_bounds__(kThreads) void k_peel_tail(
-    int32_t k0, uint32_t *__restrict__ fk0, uint32_t *__restrict__ fk1, uint32_t *__restrict__ uk0,
-    uint32_t *__restrict__ uk1, int32_t *__restrict__ urun0, int32_t *__restrict__ urun1,
-    int32_t *__restrict__ ucnt0, int32_t *__restrict__ ucnt1, int32_t *__restrict__ rank_s,
-    int32_t *__restrict__ fsize, int32_t *__restrict__ usize, uint32_t *__restrict__ blkcnt,
-    DevScalars *__restrict__ sc, GridBar *__restrict__ bar) {
-    __shared__ __attribute__((aligned(16))) uint32_t lrec[8192];
-    if (__hip_atomic_load(&sc->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-    int32_t level = k0;
-    int32_t nu = usize[level - 1];
-    if (nu == 0) return;  // the enqueued levels finished peeling
-    if (fsize[level - 1] == 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&sc->err, (uint32_t)kErrInternal);
-        return;
-    }
-    for (;;) {
-        const int p = (level - 1) & 1, q = level & 1;
-        uint32_t *us = p ? uk1 : uk0;
-        int32_t *rs = p ? urun1 : urun0;
-        int32_t *cs = p ? ucnt1 : ucnt0;
-        uint32_t *fd = q ? fk1 : fk0;
-        uint32_t *ud = q ? uk1 : uk0;
-        int32_t *rd = q ? urun1 : urun0;
-        int32_t *cd = q ? ucnt1 : ucnt0;
-        int32_t nf2 = 0, nu2 = 0;
-        if (!tail_split<M>(us, rs, cs, nu, fd, ud, rd, cd, rank_s, level, blkcnt, sc, bar, &nf2, &nu2))
-            return;
-        if (blockIdx.x == 0 && threadIdx.x == 0) { fsize[level] = nf2; usize[level] = nu2; }
-        if (!grid_barrier2(bar, &sc->err)) return;
-        if (nu2 == 0) return;
-        if (nf2 == 0) {  // impossible for a partial order; leave instead of spinning
-            if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&sc->err, (uint32_t)kErrInternal);
-            return;
-        }
-        tail_phase_a<M>(fd, nf2, ud, rd, cd, nu2, lrec, blockIdx.x, gridDim.x);
-        if (!grid_barrier2(bar, &sc->err)) return;
-        nu = nu2;
-        ++level;
-    }
-}
-
-// Single-workgroup tail (usable inside captured graphs, where cooperative
-// launches are not): one block finishes the levels from k0 on, with block
-// barriers only.  Meant for the few points left after the enqueued levels.
-template <int M>
-__global__ __launch_bounds__(kThreads) void k_peel_tail_block(
-    int32_t k0, uint32_t *__restrict__ fk0, uint32_t *__restrict__ fk1, uint32_t *__restrict__ uk0,
-    uint32_t *__restrict__ uk1, int32_t *__restrict__ urun0, int32_t *__restrict__ urun1,
-    int32_t *__restrict__ ucnt0, int32_t *__restrict__ ucnt1, int32_t *__restrict__ rank_s,
-    int32_t *__restrict__ fsize, int32_t *__restrict__ usize, DevScalars *__restrict__ sc) {
+__device__ void tail_levels_one_block(int32_t level, int32_t nu, uint32_t *__restrict__ fk0,
+                                      uint32_t *__restrict__ fk1, uint32_t *__restrict__ uk0,
+                                      uint32_t *__restrict__ uk1, int32_t *__restrict__ urun0,
+                                      int32_t *__restrict__ urun1, int32_t *__restrict__ ucnt0,
+                                      int32_t *__restrict__ ucnt1, int32_t *__restrict__ rank_s,
+                                      int32_t *__restrict__ fsize, int32_t *__restrict__ usize,
+                                      DevScalars *__restrict__ sc, uint32_t *lrec, uint32_t *lds) {
     constexpr int MP = rec_stride(M);
-    __shared__ __attribute__((aligned(16))) uint32_t lrec[8192];
-    __shared__ uint32_t lds[17];
-    if (sc->err) return;
-    int32_t level = k0;
-    int32_t nu = usize[level - 1];
-    if (nu == 0) return;
-    if (fsize[level - 1] == 0) {
-        if (threadIdx.x == 0) atomicOr(&sc->err, (uint32_t)kErrInternal);
-        return;
-    }
     for (;;) {
         const int p = (level - 1) & 1, q = level & 1;
         const uint32_t *us = p ? uk1 : uk0;
@@ -502,6 +452,77 @@ __global__ __launch_bounds__(kThreads) void k_peel_tail_block(
     }
 }
 
+template <int M>
+__global__ __launch_bounds__(kThreads) void k_peel_tail(
+    int32_t k0, uint32_t *__restrict__ fk0, uint32_t *__restrict__ fk1, uint32_t *__restrict__ uk0,
+    uint32_t *__restrict__ uk1, int32_t *__restrict__ urun0, int32_t *__restrict__ urun1,
+    int32_t *__restrict__ ucnt0, int32_t *__restrict__ ucnt1, int32_t *__restrict__ rank_s,
+    int32_t *__restrict__ fsize, int32_t *__restrict__ usize, uint32_t *__restrict__ blkcnt,
+    DevScalars *__restrict__ sc, GridBar *__restrict__ bar) {
+    __shared__ __attribute__((aligned(16))) uint32_t lrec[8192];
+    __shared__ uint32_t lds1[17];
+    if (__hip_atomic_load(&sc->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    int32_t level = k0;
+    int32_t nu = usize[level - 1];
+    if (nu == 0) return;  // the enqueued levels finished peeling
+    if (fsize[level - 1] == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&sc->err, (uint32_t)kErrInternal);
+        return;
+    }
+    if (nu <= kTailOneBlockMax) {  // few points left: one work-group, no grid barriers
+        if (blockIdx.x == 0)
+            tail_levels_one_block<M>(level, nu, fk0, fk1, uk0, uk1, urun0, urun1, ucnt0, ucnt1,
+                                     rank_s, fsize, usize, sc, lrec, lds1);
+        return;
+    }
+    for (;;) {
+        const int p = (level - 1) & 1, q = level & 1;
+        uint32_t *us = p ? uk1 : uk0;
+        int32_t *rs = p ? urun1 : urun0;
+        int32_t *cs = p ? ucnt1 : ucnt0;
+        uint32_t *fd = q ? fk1 : fk0;
+        uint32_t *ud = q ? uk1 : uk0;
+        int32_t *rd = q ? urun1 : urun0;
+        int32_t *cd = q ? ucnt1 : ucnt0;
+        int32_t nf2 = 0, nu2 = 0;
+        if (!tail_split<M>(us, rs, cs, nu, fd, ud, rd, cd, rank_s, level, blkcnt, sc, bar, &nf2, &nu2))
+            return;
+        if (blockIdx.x == 0 && threadIdx.x == 0) { fsize[level] = nf2; usize[level] = nu2; }
+        if (!grid_barrier2(bar, &sc->err)) return;
+        if (nu2 == 0) return;
+        if (nf2 == 0) {  // impossible for a partial order; leave instead of spinning
+            if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&sc->err, (uint32_t)kErrInternal);
+            return;
+        }
+        tail_phase_a<M>(fd, nf2, ud, rd, cd, nu2, lrec, blockIdx.x, gridDim.x);
+        if (!grid_barrier2(bar, &sc->err)) return;
+        nu = nu2;
+        ++level;
+    }
+}
+
+// Single-workgroup tail (usable inside captured graphs, where cooperative
+// launches are not): one block finishes the levels from k0 on.  Meant for the
+// few points left after the enqueued levels.
+template <int M>
+__global__ __launch_bounds__(kThreads) void k_peel_tail_block(
+    int32_t k0, uint32_t *__restrict__ fk0, uint32_t *__restrict__ fk1, uint32_t *__restrict__ uk0,
+    uint32_t *__restrict__ uk1, int32_t *__restrict__ urun0, int32_t *__restrict__ urun1,
+    int32_t *__restrict__ ucnt0, int32_t *__restrict__ ucnt1, int32_t *__restrict__ rank_s,
+    int32_t *__restrict__ fsize, int32_t *__restrict__ usize, DevScalars *__restrict__ sc) {
+    __shared__ __attribute__((aligned(16))) uint32_t lrec[8192];
+    __shared__ uint32_t lds[17];
+    if (sc->err) return;
+    const int32_t nu = usize[k0 - 1];
+    if (nu == 0) return;
+    if (fsize[k0 - 1] == 0) {
+        if (threadIdx.x == 0) atomicOr(&sc->err, (uint32_t)kErrInternal);
+        return;
+    }
+    tail_levels_one_block<M>(k0, nu, fk0, fk1, uk0, uk1, urun0, urun1, ucnt0, ucnt1, rank_s, fsize,
+                             usize, sc, lrec, lds);
+}
+
 // a3: number of fronts and the last admitted front l = rank of the K-th
 // smallest rank (0-based position K-1).
 __global__ void k_last_front(const int32_t *__restrict__ fsize, const int32_t *__restrict__ usize,
@@ -519,6 +540,9 @@ __global__ void k_last_front(const int32_t *__restrict__ fsize, const int32_t *_
         cum += fsize[k];
     }
     sc->num_fronts = L;
+    // host feedback: the front count, then the points left after each level
+    sc->fb[0] = L;
+    for (int32_t k = 0; k < L && k < kProfLevels; ++k) sc->fb[1 + k] = usize[k];
     sc->last_front = l;
     sc->last_front_size = fsize[l];
     sc->n_before = cum;
@@ -545,7 +569,8 @@ static hipError_t launch_peel(const SortViews &v, const LaunchCfg &cfg, hipStrea
                                v.fsize, v.usize, lb_cur, lb_next, v.sc);
         }
         if (cfg.bitsets)
-            run_bit_level(v, v.fk[q], v.uk[q], v.urun[q], v.ucnt[q], k, ga, s);
+            run_bit_level(v, v.fk[q], v.uk[q], v.urun[q], v.ucnt[q], k, ga,
+                          k < kProfLevels ? cfg.fprev[k] : 0, s);
         else
             hipLaunchKernelGGL(k_phase_a<M>, dim3(ga), dim3(kThreads), 0, s, v.fk[q], v.uk[q],
                                v.urun[q], v.ucnt[q], k, v.fsize, v.usize, v.work, v.sc);

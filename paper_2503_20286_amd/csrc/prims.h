@@ -43,6 +43,30 @@ __device__ __forceinline__ T wave_max(T v) {
     return v;
 }
 
+// Inclusive scan (OR or sum) over a wave's 64 lanes with data-parallel
+// primitive moves instead of LDS permutes: shifts by 1, 2, 4 and 8 lanes
+// within each row of 16, then lane 15 broadcast into rows 1 and 3 and lane 31
+// into rows 2 and 3.  A lane whose source lies outside its row (or whose row
+// a broadcast skips) reads 0, the identity of both operations.  Every lane of
+// the wave must be active.
+template <bool kOr>
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
+#define NSGA3_DPP_STEP(ctrl, rows)                                                          \
+    {                                                                                       \
+        const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, ctrl, rows, 0xf, \
+                                                                 false);                    \
+        x = kOr ? (x | t) : (x + t);                                                        \
+    }
+    NSGA3_DPP_STEP(0x111, 0xf)  // row_shr:1
+    NSGA3_DPP_STEP(0x112, 0xf)  // row_shr:2
+    NSGA3_DPP_STEP(0x114, 0xf)  // row_shr:4
+    NSGA3_DPP_STEP(0x118, 0xf)  // row_shr:8
+    NSGA3_DPP_STEP(0x142, 0xa)  // row_bcast:15
+    NSGA3_DPP_STEP(0x143, 0xc)  // row_bcast:31
+#undef NSGA3_DPP_STEP
+    return x;
+}
+
 // Block-wide exclusive scan of one uint32 per thread (blockDim.x a multiple of
 // 64, at most 1024).  Returns the exclusive prefix; *total receives the sum.
 // `lds` needs blockDim.x / 64 + 1 entries.
@@ -50,11 +74,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *l
     const uint32_t lane = lane_id();
     const uint32_t wid = threadIdx.x / kWave;
     const uint32_t nw = blockDim.x / kWave;
-    uint32_t incl = v;
-    for (int o = 1; o < kWave; o <<= 1) {
-        uint32_t t = __shfl_up(incl, o, 64);
-        if (lane >= (uint32_t)o) incl += t;
-    }
+    const uint32_t incl = wave_inclusive_scan<false>(v);
     if (lane == kWave - 1) lds[wid] = incl;
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -98,3 +98,27 @@ def test_injected_allocation_failure_then_success(monkeypatch):
     assert torch.equal(plan.results[0].selected, torch.from_numpy(g["selected"]).cuda())
     plan.close()
     ctx.close()
+
+
+def test_repeated_calls_follow_the_previous_level_profile():
+    """A context sizes each call's peeling launches from the previous call's
+    level sizes: the levels it enqueues, the table-build grids, and the last
+    levels finished by one work-group.  Repeating a workload takes the
+    one-work-group tail; switching workloads makes the expectation stale in
+    both directions (too many enqueued levels, or a tail too large for one
+    work-group, which the grid then peels).  Every call must match the
+    oracle exactly."""
+    import paper_2503_20286_amd as nsga3
+    cases = {
+        "ties": workloads.make("ties", N=8000, seed=41),
+        "large": workloads.make("large", N=6000, seed=42),
+        "small": workloads.make("small", N=200, seed=43),
+    }
+    refsel = {k: oracle.select(w.objs, w.refs, w.K, with_counts=True) for k, w in cases.items()}
+    ctx = nsga3.Context(0)
+    for name in ("ties", "ties", "ties", "large", "ties", "large", "large", "small", "ties"):
+        w = cases[name]
+        print(name, w.N, w.M, refsel[name].num_fronts, flush=True)
+        g = gpu_select(w.objs, w.refs, w.K, ctx=ctx)
+        _zero(compare_full(w.objs, w.refs, w.K, g, s=refsel[name]))
+    ctx.close()
