@@ -14,9 +14,11 @@ phase (the dominance counts): algorithmic work M*N*(N-1)/2 pair-objective
 compares per launch (every unordered pair decided once) divided by the phase's
 event-timed duration, against the vector-ALU rate 256 CUs x 64 lanes x 2.4 GHz.
 The block-bitset kernels decide 64 pairs per probe, so this is an effective
-pair-decision rate, not a VALU utilisation, and it can exceed 1.  traffic is
-the phase's HBM bytes from FETCH_SIZE / WRITE_SIZE counters
-(profiles/dominance_count_large_traffic.json).
+pair-decision rate, not a VALU utilisation, and it can exceed 1; the issue
+utilisation is roofline.valu_issue: the phase's counted VALU instructions
+(SQ_INSTS_VALU, profiles/dominance_count_large_counters.json) over its event
+time against 1024 SIMDs x 2.4 GHz / 4.  traffic is the phase's HBM bytes from
+FETCH_SIZE / WRITE_SIZE counters (profiles/dominance_count_large_traffic.json).
 
 The float64 oracle runs once on the whole workload: its wall time is the
 cpu_baseline, and its outputs are compared element by element with the timed
@@ -40,6 +42,8 @@ if ROOT not in sys.path:
 METRIC = "merged-pop points/sec through NSGA-III selection (N=200k,M=5); batched sel/s"
 PEAK_CMP_PER_S = 256 * 64 * 2.4e9          # vector-ALU lane operations per second
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dominance_count_large_traffic.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "dominance_count_large_counters.json")
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4       # wave64 VALU instructions per second
 
 
 def parse():
@@ -578,6 +582,15 @@ def main():
             tr = json.load(fh)
         if tr.get("workload") == args.workload:
             traffic = tr.get("bytes_per_launch")
+    valu = None
+    if os.path.exists(COUNTERS_FILE):
+        with open(COUNTERS_FILE) as fh:
+            cn = json.load(fh)
+        if cn.get("workload") == args.workload and cn.get("count_phase_valu_per_launch"):
+            v = cn["count_phase_valu_per_launch"]
+            valu = {"instructions_per_launch": v,
+                    "frac_of_issue_peak": v / (t_dom * VALU_ISSUE_PER_S),
+                    "source": os.path.relpath(COUNTERS_FILE, ROOT)}
     res = {
         "metric": METRIC,
         "value": N / (ms_per_step / 1e3),
@@ -614,6 +627,9 @@ def main():
                     "exceed 1",
             "frac_counts_and_peeling": cmp_per_launch / ((phases["dominance_count"] + phases["peel"])
                                                           / 1e3) / PEAK_CMP_PER_S,
+            # counted VALU instructions of the phase (rocprofv3 SQ_INSTS_VALU)
+            # over this run's phase time against 1024 SIMDs x 2.4 GHz / 4
+            "valu_issue": valu,
         },
         "phases_ms": phases,
         "streaming_phases_gb_s": {
