@@ -458,7 +458,12 @@ nsga3_status noalloc_setup(int dev, NoallocDevice **out) {
 extern "C" {
 
 const char *nsga3_status_string(nsga3_status s) {
-    switch (s) {
+    // a C caller may pass any int: read the argument's bits, not the enum
+    // value (a load outside the enumerators' range is undefined in C++)
+    int v = 0;
+    static_assert(sizeof(s) == sizeof(v), "status is int-sized");
+    memcpy(&v, &s, sizeof(v));
+    switch (v) {
         case NSGA3_OK: return "ok";
         case NSGA3_E_INVALID: return "invalid argument";
         case NSGA3_E_NONFINITE: return "non-finite objective or invalid reference direction";
