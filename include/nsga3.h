@@ -334,6 +334,18 @@ void nsga3_plan_destroy(nsga3_plan *plan);
  * number of entries to *count (host). */
 nsga3_status nsga3_tuned_shapes(const nsga3_ctx *ctx, int32_t *out, int32_t cap, int32_t *count);
 
+/* Keep the autotuner's choices across processes.  nsga3_tuned_save writes the
+ * context's tuned shapes to the text file `path` (host path; written whole to
+ * "<path>.tmp" and renamed): a header naming the device architecture and CU
+ * count, then one line per (M, N range).  nsga3_tuned_load merges such a file
+ * into the context (entries replace those of the same key), so plans created
+ * afterwards with autotuning time only the groups still missing.  Errors:
+ * NSGA3_E_INVALID for a missing, unreadable or malformed file (nothing is
+ * loaded), NSGA3_E_UNSUPPORTED for a file tuned on another architecture or CU
+ * count.  Host-only; neither touches the device. */
+nsga3_status nsga3_tuned_save(const nsga3_ctx *ctx, const char *path);
+nsga3_status nsga3_tuned_load(nsga3_ctx *ctx, const char *path);
+
 /* Engine stages (index into the arrays of nsga3_plan_stage_times):
  *   0 keys and references, 1 radix histogram, 2 radix scatter, 3 sorted records,
  *   4 dominance counts, 5 split counts, 6 split writes, 7 peeling decrements,

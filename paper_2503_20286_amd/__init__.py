@@ -16,6 +16,7 @@ from ._native import (  # noqa: F401
     NativeError, Plan, Selection, STATUS, default_context, exported_symbols, header_symbols, lib_path, load, select, version,
     workspace_size, select_noalloc, alloc_outputs, rvea_select, RveaSelection,
     hype_select, HypeSelection, sbx_pm, gather_rows,
+    OK, E_INVALID, E_NONFINITE, E_NOMEM, E_HIP, E_UNSUPPORTED,
 )
 
 __all__ = ["select", "Context", "Plan", "Selection", "Info", "NativeError", "load", "version",

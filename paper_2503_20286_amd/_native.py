@@ -19,6 +19,7 @@ def lib_path() -> str:
 
 STATUS = {0: "NSGA3_OK", -1: "NSGA3_E_INVALID", -2: "NSGA3_E_NONFINITE", -3: "NSGA3_E_NOMEM",
           -4: "NSGA3_E_HIP", -5: "NSGA3_E_UNSUPPORTED"}
+OK, E_INVALID, E_NONFINITE, E_NOMEM, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 NUM_PHASES = 6
 PHASES = ("prep_sort", "dominance_count", "peel", "normalize", "associate", "niching")
 ASSOC_FP32 = 0
@@ -118,6 +119,10 @@ def load():
         L.nsga3_plan_stage_times.restype = ctypes.c_int
         L.nsga3_tuned_shapes.argtypes = [P, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)]
         L.nsga3_tuned_shapes.restype = ctypes.c_int
+        L.nsga3_tuned_save.argtypes = [P, ctypes.c_char_p]
+        L.nsga3_tuned_save.restype = ctypes.c_int
+        L.nsga3_tuned_load.argtypes = [P, ctypes.c_char_p]
+        L.nsga3_tuned_load.restype = ctypes.c_int
         L.nsga3_plan_destroy.argtypes = [P]
         L.nsga3_plan_destroy.restype = None
         L.nsga3_version.argtypes = []
@@ -203,6 +208,18 @@ class Context:
             raise NativeError("nsga3_tuned_shapes", rc, self._lib)
         keys = ("M", "n_range", "pa_items", "tail_max", "tail_front")
         return [dict(zip(keys, buf[5 * q:5 * q + 5])) for q in range(cnt.value)]
+
+    def save_tuned(self, path):
+        """Write the tuned shapes to a text file (nsga3_tuned_save)."""
+        rc = self._lib.nsga3_tuned_save(self._h, os.fsencode(path))
+        if rc != 0:
+            raise NativeError("nsga3_tuned_save", rc, self._lib)
+
+    def load_tuned(self, path):
+        """Merge tuned shapes from a file written by save_tuned (nsga3_tuned_load)."""
+        rc = self._lib.nsga3_tuned_load(self._h, os.fsencode(path))
+        if rc != 0:
+            raise NativeError("nsga3_tuned_load", rc, self._lib)
 
     def phase_times(self):
         """(per-phase summed milliseconds, number of calls) since profiling was enabled."""

@@ -1,6 +1,7 @@
 // C ABI of libnsga3: context, workspace and the environmental-selection entry
 // point.  Host code only; the kernels live in dominance.hip, select.hip and
 // sort_scan.hip.
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -48,6 +49,7 @@ struct EngineShape {        // per-instance work-item shape of the batched engin
 
 struct nsga3_ctx {
     int device;
+    char arch[64];                  // device architecture name (tuned-shape cache key)
     nsga3_options opt;
     std::map<std::pair<int, int>, EngineShape> tuned;  // (M, N range) -> fastest shape
     int num_cus;
@@ -497,6 +499,9 @@ nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt)
     nsga3_ctx *c = new (std::nothrow) nsga3_ctx();
     if (!c) return NSGA3_E_NOMEM;
     c->device = device;
+    snprintf(c->arch, sizeof(c->arch), "%s", prop.gcnArchName);
+    for (char *q = c->arch; *q; ++q)
+        if (*q == ' ' || *q == '\n') *q = '_';
     c->opt.assoc = NSGA3_ASSOC_FP32;
     c->opt.autotune = 0;
     c->opt.max_workspace_bytes = 0;
@@ -824,6 +829,8 @@ static const EngineShape kShapeCandidates[] = {
     {32, 0, 0},
 };
 
+constexpr int kTuneReps = 3;  // timed runs per candidate shape (median taken)
+
 // Times the whole engine pipeline on one group of instances (all of one M),
 // eagerly on `s`, for every candidate shape; returns the fastest.  The group's
 // instances use their own workspaces; their outputs are overwritten (the plan
@@ -874,8 +881,10 @@ static nsga3_status tune_group(nsga3_ctx *ctx, const std::vector<nsga3::EInst> &
             st = NSGA3_E_HIP;
             break;
         }
+        // one untimed run, then the median of kTuneReps timed runs
+        float reps[kTuneReps];
         float ms = 0.0f;
-        for (int rep = 0; rep < 2 && st == NSGA3_OK; ++rep) {  // the second run is timed
+        for (int rep = 0; rep <= kTuneReps && st == NSGA3_OK; ++rep) {
             hipError_t e = hipEventRecord(e0, s);
             if (e == hipSuccess) e = engine_init(d_inst, d_state, d_glob, nb, 2, s);
             if (e == hipSuccess) e = engine_launch(M, d_inst, d_state, 0, nb, d_glob, nullptr, kSDom, grid, s);
@@ -891,6 +900,11 @@ static nsga3_status tune_group(nsga3_ctx *ctx, const std::vector<nsga3::EInst> &
                 (void)hipGetLastError();
                 st = NSGA3_E_HIP;
             }
+            if (rep > 0) reps[rep - 1] = ms;
+        }
+        if (st == NSGA3_OK) {
+            std::sort(reps, reps + kTuneReps);
+            ms = reps[kTuneReps / 2];
         }
         if (st == NSGA3_OK && (best_ms < 0.0f || ms < best_ms)) {
             best_ms = ms;
@@ -1323,6 +1337,57 @@ nsga3_status nsga3_tuned_shapes(const nsga3_ctx *ctx, int32_t *out, int32_t cap,
         ++n;
     }
     *count = n;
+    return NSGA3_OK;
+}
+
+// Tuned-shape cache file: a header line "nsga3-tuned-shapes 1 <arch> <CUs>",
+// then one line "M n_range pa_items tail_max tail_front" per entry.
+nsga3_status nsga3_tuned_save(const nsga3_ctx *ctx, const char *path) {
+    if (!ctx || !path || !*path) return NSGA3_E_INVALID;
+    char tmp[4096];
+    if (snprintf(tmp, sizeof(tmp), "%s.tmp", path) >= (int)sizeof(tmp)) return NSGA3_E_INVALID;
+    FILE *f = fopen(tmp, "w");
+    if (!f) return NSGA3_E_INVALID;
+    bool ok = fprintf(f, "nsga3-tuned-shapes 1 %s %d\n", ctx->arch, ctx->num_cus) > 0;
+    for (const auto &kv : ctx->tuned)
+        ok = ok && fprintf(f, "%d %d %d %d %d\n", kv.first.first, kv.first.second,
+                           kv.second.pa_items, kv.second.tail_max, kv.second.tail_front) > 0;
+    ok = (fclose(f) == 0) && ok;
+    if (!ok || rename(tmp, path) != 0) {
+        (void)remove(tmp);
+        return NSGA3_E_INVALID;
+    }
+    return NSGA3_OK;
+}
+
+nsga3_status nsga3_tuned_load(nsga3_ctx *ctx, const char *path) {
+    if (!ctx || !path) return NSGA3_E_INVALID;
+    FILE *f = fopen(path, "r");
+    if (!f) return NSGA3_E_INVALID;
+    char magic[32] = {0}, arch[64] = {0};
+    int version = 0, cus = 0;
+    nsga3_status st = NSGA3_OK;
+    if (fscanf(f, "%31s %d %63s %d", magic, &version, arch, &cus) != 4 ||
+        strcmp(magic, "nsga3-tuned-shapes") != 0 || version != 1) {
+        st = NSGA3_E_INVALID;
+    } else if (strcmp(arch, ctx->arch) != 0 || cus != ctx->num_cus) {
+        st = NSGA3_E_UNSUPPORTED;  // tuned on another device
+    }
+    std::vector<std::pair<std::pair<int, int>, EngineShape>> rows;
+    while (st == NSGA3_OK) {
+        int m = 0, r = 0, pa = 0, tm = 0, tf = 0;
+        const int got = fscanf(f, "%d %d %d %d %d", &m, &r, &pa, &tm, &tf);
+        if (got == EOF) break;
+        if (got != 5 || m < 2 || m > 16 || r < 0 || r > 3 || pa < 1 || pa > (1 << 20) || tm < 0 ||
+            tf < 0) {
+            st = NSGA3_E_INVALID;
+            break;
+        }
+        rows.push_back({{m, r}, EngineShape{pa, tm, tf}});
+    }
+    fclose(f);
+    if (st != NSGA3_OK) return st;  // nothing is taken from a rejected file
+    for (const auto &row : rows) ctx->tuned[row.first] = row.second;
     return NSGA3_OK;
 }
 

@@ -88,6 +88,8 @@ int main(void)
     nsga3_plan_destroy(NULL);
     int32_t cnt = 0;
     CHECK(nsga3_tuned_shapes(NULL, NULL, 0, &cnt) == NSGA3_E_INVALID);
+    CHECK(nsga3_tuned_save(NULL, "unused.txt") == NSGA3_E_INVALID);
+    CHECK(nsga3_tuned_load(NULL, "unused.txt") == NSGA3_E_INVALID);
     double ms[NSGA3_NUM_PHASES];
     int64_t calls = 0;
     CHECK(nsga3_phase_times(NULL, ms, &calls) == NSGA3_E_INVALID);

@@ -236,6 +236,53 @@ def test_autotuned_plan_matches_single_calls():
     ctx.close()
 
 
+def test_tuned_shapes_persist_across_contexts(tmp_path):
+    """nsga3_tuned_save / nsga3_tuned_load: a second context that loads the
+    first one's file holds the same shapes, and its autotuned plan (which then
+    times nothing) gives the single calls' results; malformed files and files
+    from another device are rejected without changing the context."""
+    import torch
+    import paper_2503_20286_amd as nsga3
+    ws = workloads.make_batch(10, n_lo=100, n_hi=9000, base_seed=8250)
+    probs = _dev(ws)
+    ctx = nsga3.Context(0, autotune=True)
+    plan = nsga3.Plan(probs, ctx=ctx)
+    plan.close()
+    shapes = ctx.tuned_shapes()
+    assert shapes
+    path = tmp_path / "tuned.txt"
+    ctx.save_tuned(path)
+    ctx.close()
+    ctx2 = nsga3.Context(0, autotune=True)
+    assert ctx2.tuned_shapes() == []
+    ctx2.load_tuned(path)
+    assert ctx2.tuned_shapes() == shapes
+    plan2 = nsga3.Plan(probs, ctx=ctx2)
+    assert ctx2.tuned_shapes() == shapes  # every group came from the file
+    plan2.launch()
+    torch.cuda.synchronize()
+    _check_against_single(plan2, probs, "loaded")
+    plan2.close()
+    lines = path.read_text().splitlines()
+    bad = tmp_path / "bad.txt"
+    bad.write_text("\n".join(lines + ["5 1 8 -3 0"]) + "\n")  # negative tail length
+    other = tmp_path / "other.txt"
+    head = lines[0].split()
+    other.write_text("\n".join([" ".join(head[:3] + [str(int(head[3]) + 1)])] + lines[1:]) + "\n")
+    ctx3 = nsga3.Context(0)
+    with pytest.raises(nsga3.NativeError) as e1:
+        ctx3.load_tuned(bad)
+    assert e1.value.code == nsga3.E_INVALID
+    with pytest.raises(nsga3.NativeError) as e2:
+        ctx3.load_tuned(other)
+    assert e2.value.code == nsga3.E_UNSUPPORTED
+    with pytest.raises(nsga3.NativeError):
+        ctx3.load_tuned(tmp_path / "missing.txt")
+    assert ctx3.tuned_shapes() == []
+    ctx3.close()
+    ctx2.close()
+
+
 def test_plan_rejects_bad_descriptor():
     import torch
     import paper_2503_20286_amd as nsga3
