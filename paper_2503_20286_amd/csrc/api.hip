@@ -540,9 +540,9 @@ nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt)
     c->bitsets = true;
     if (const char *e = getenv("NSGA3_PAIRWISE")) c->bitsets = atoi(e) == 0;
     // work-groups per CU of the per-level decrement kernels: the bitset level
-    // kernel's 34 KiB chunks let four stay resident (peel at N = 200k, M = 5:
-    // 1.74 ms with 4 per CU, 1.76 with 8, 1.78 with 16, 1.90 with 3)
-    c->phase_a_bpc = c->bitsets ? 4 : 8;
+    // kernel's 24 KiB chunks let six stay resident (peel at N = 200k, M = 5:
+    // 1.090 ms with 6 per CU, 1.093 with 8, 1.111 with 4)
+    c->phase_a_bpc = c->bitsets ? 6 : 8;
     // NSGA3_TAIL_BLOCK=1: finish peeling in one workgroup instead of the
     // cooperative grid (the form captured graphs use; same results)
     c->tail_block = false;
@@ -662,7 +662,7 @@ nsga3_status nsga3_select_noalloc(const float *objs, int64_t N, int32_t M, const
     a.ws = d->scratch;
     a.cfg.num_cus = d->num_cus;
     a.cfg.peel_blocks_per_cu = d->peel_bpc[M];
-    a.cfg.phase_a_blocks_per_cu = 4;
+    a.cfg.phase_a_blocks_per_cu = 6;
     a.cfg.host_levels = kDefaultHostLevels;
     a.cfg.bitsets = true;
     a.cfg.tail_block = true;          // no cooperative launch: capture-safe

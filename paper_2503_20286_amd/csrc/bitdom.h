@@ -127,6 +127,12 @@ template <int M>
 __host__ __device__ constexpr int count_chunk() { return chunk_blocks<kLdsCountDwords, M>(); }
 template <int M>
 __host__ __device__ constexpr int level_chunk() { return chunk_blocks<kLdsLevelDwords, M>(); }
+// The single-call level kernel stages smaller chunks than the engine's items:
+// 24 KiB lets six of its work-groups stay resident per CU (peel at N = 200k,
+// M = 5: 1.090 ms with 24 KiB and six per CU, 1.112 with 34 KiB and four).
+constexpr int kLdsLevelKernelDwords = 6264;
+template <int M>
+__host__ __device__ constexpr int level_kernel_chunk() { return chunk_blocks<kLdsLevelKernelDwords, M>(); }
 
 // ---------------------------------------------------------------------------
 // Tables: one wave per block of 64 consecutive list entries.
@@ -339,6 +345,55 @@ __device__ __forceinline__ void fwd_level_item(const uint32_t *__restrict__ tabs
         const int32_t run_lo = vld(&urun[jbase]);
         const int32_t run_hi = vld(&urun[min(jbase + kWave * TJ - 1, nu - 1)]);
         fwd_blocks<M, TJ>(lt, nb, run_lo, run_hi, kj, run, cnt);
+#pragma unroll
+        for (int u = 0; u < TJ; ++u) {
+            const int32_t q = jbase + u * kWave + lane;
+            if (q < nu && cnt[u]) atomicSub(&ucnt[q], cnt[u]);
+        }
+    }
+}
+
+// One tile of kFwdThreads * TJ remaining points against ng consecutive chunks
+// of cb front tables from block b0 on: the points' keys stay in registers
+// while each chunk is staged in LDS in turn, and each point's decrement goes
+// out with one atomic.  A chunk that starts at or after the tile's last run
+// ends the sweep (later chunks start later still).
+template <int M, int TJ>
+__device__ __forceinline__ void fwd_level_group(const uint32_t *__restrict__ tabs, int32_t b0,
+                                                int32_t cb, int32_t ng, int32_t nblk,
+                                                const uint32_t *__restrict__ uk,
+                                                const int32_t *__restrict__ urun, int32_t nu,
+                                                int32_t *__restrict__ ucnt, int32_t jt,
+                                                uint32_t *lt) {
+    constexpr int TS = blk_stride(M);
+    constexpr int TILE = kFwdThreads * TJ;
+    if (jt * TILE >= nu) return;
+    const int32_t last_run = vld(&urun[min((jt + 1) * TILE, nu) - 1]);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = (int)lane_id();
+    const int32_t jbase = jt * TILE + w * kWave * TJ;
+    const bool active = jbase < nu;  // uniform in the wave
+    uint32_t kj[TJ][M];
+    int32_t run[TJ], cnt[TJ];
+    int32_t run_lo = 0, run_hi = 0;
+#pragma unroll
+    for (int u = 0; u < TJ; ++u) cnt[u] = 0;
+    if (active) {
+        load_points<M, TJ>(uk, urun, nu, jbase, lane, kj, run);
+        run_lo = vld(&urun[jbase]);
+        run_hi = vld(&urun[min(jbase + kWave * TJ - 1, nu - 1)]);
+    }
+    for (int32_t g = 0; g < ng; ++g) {
+        const int32_t bs = b0 + g * cb;
+        if (bs >= nblk) break;
+        if ((int32_t)vld(&tabs[(size_t)bs * TS]) >= last_run) break;
+        const int32_t nb = min(cb, nblk - bs);
+        __syncthreads();  // every wave is done with the previous chunk
+        stage_tables<M>(lt, tabs, bs, nb);
+        __syncthreads();
+        if (active) fwd_blocks<M, TJ>(lt, nb, run_lo, run_hi, kj, run, cnt);
+    }
+    if (active) {
 #pragma unroll
         for (int u = 0; u < TJ; ++u) {
             const int32_t q = jbase + u * kWave + lane;

@@ -159,6 +159,13 @@ constexpr int kFwdLevelTiles = 1;  // remaining-list tiles per item (2 and 4 mea
 // 1.64 to 1.57 ms (the all-pairs counts keep kTJ = 2, their best).
 constexpr int kLevelTJ = 3;
 constexpr int kLevelTileJ = kFwdThreads * kLevelTJ;
+// Chunks of front tables a level work item sweeps for its tile (fewer on
+// levels whose items would not fill two rounds of the grid): 2 took the peel
+// at N = 200k, M = 5 from 1.127 to 1.115 ms, 4 to 1.16.
+#ifndef NSGA3_LEVEL_CHUNKS
+#define NSGA3_LEVEL_CHUNKS 2
+#endif
+constexpr int kLevelChunksPerItem = NSGA3_LEVEL_CHUNKS;
 
 template <int M>
 __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
@@ -167,7 +174,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
     const int32_t *__restrict__ fsize, const int32_t *__restrict__ usize,
     uint32_t *__restrict__ work, const DevScalars *__restrict__ sc) {
     constexpr int TS = blk_stride(M);
-    constexpr int CB = level_chunk<M>();
+    constexpr int CB = level_kernel_chunk<M>();
     __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
     __shared__ int32_t s_item;
     if (sc->err) return;
@@ -176,19 +183,21 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
     if (nf == 0 || nu == 0) return;
     const int32_t nblk = (nf + kBlk - 1) / kBlk;
     constexpr int T = kFwdLevelTiles;
+    static_assert(T == 1, "level items cover one remaining-list tile");
     const int32_t nJG = ((nu + kLevelTileJ - 1) / kLevelTileJ + T - 1) / T;
     // small levels: fewer tables per item while the items still fit in one
     // round of the grid (shorter items, same number of rounds)
     int32_t cb = CB;
     while (cb > 1 && (int64_t)((nblk + cb / 2 - 1) / (cb / 2)) * nJG <= (int64_t)gridDim.x) cb >>= 1;
     const int32_t nIC = (nblk + cb - 1) / cb;
-    const int64_t nitems = (int64_t)nIC * nJG;
+    int32_t ng = kLevelChunksPerItem;
+    while (ng > 1 && (int64_t)((nIC + ng - 1) / ng) * nJG < 2 * (int64_t)gridDim.x) ng >>= 1;
+    const int64_t nitems = (int64_t)((nIC + ng - 1) / ng) * nJG;
     int64_t item = blockIdx.x;
     while (item < nitems) {
-        const int32_t ic = (int32_t)(item / nJG);
+        const int32_t ig = (int32_t)(item / nJG);
         const int32_t jg = (int32_t)(item % nJG);
-        const int32_t b0 = ic * cb;
-        fwd_level_item<M, T, kLevelTJ>(tabs, b0, min(cb, nblk - b0), uk, urun, nu, ucnt, jg * T, lt);
+        fwd_level_group<M, kLevelTJ>(tabs, ig * ng * cb, cb, ng, nblk, uk, urun, nu, ucnt, jg, lt);
         if (threadIdx.x == 0) s_item = (int32_t)(gridDim.x + atomicAdd(&work[level], 1u));
         __syncthreads();  // every wave is done with lt
         item = s_item;
