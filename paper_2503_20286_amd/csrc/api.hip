@@ -63,6 +63,7 @@ struct nsga3_ctx {
     int out_mode;                   // NSGA3_SEPARATE_OUT: LaunchCfg::out_mode
     int fixed_levels;               // > 0: always enqueue this many peeling levels
     double tail_work;               // peeling work left for the one-work-group tail
+    int32_t lds_build_max;          // LaunchCfg::lds_build_max
     volatile int32_t *last_fronts;  // pinned: front count, then level sizes, of the latest call
     std::vector<hipEvent_t> ev_pool;   // NSGA3_NUM_PHASES + 1 events per recorded call
     size_t ev_used;
@@ -219,6 +220,9 @@ struct PhaseMarks {
 // thousandth of the chip's lanes, so only nearly empty levels belong there
 // (N = 200k, M = 5: peel 1.15 ms at 1e4 or 3e4, 1.21 at 1e5, 1.42 at 4e5).
 constexpr double kTailPairWork = 1.0e4;
+// Largest expected front (points) whose tables the level kernel builds in LDS
+// per item instead of a table-build launch.
+constexpr int32_t kLevelLdsBuildMax = 8192;
 
 LaunchCfg ctx_cfg(const nsga3_ctx *ctx, int M, int64_t N) {
     LaunchCfg cfg;
@@ -228,6 +232,7 @@ LaunchCfg ctx_cfg(const nsga3_ctx *ctx, int M, int64_t N) {
     cfg.bitsets = ctx->bitsets;
     cfg.tail_block = ctx->tail_block;
     cfg.out_mode = ctx->out_mode;
+    cfg.lds_build_max = ctx->lds_build_max;
     // The previous call's front count and level sizes arrive asynchronously
     // in pinned memory; they only size launches (a stale or torn read shifts
     // work between the enqueued levels and the tail, never the results).
@@ -556,6 +561,10 @@ nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt)
     // last levels) at or below which those levels go to one work-group
     c->tail_work = kTailPairWork;
     if (const char *e = getenv("NSGA3_TAIL_WORK")) c->tail_work = atof(e);
+    // NSGA3_LEVEL_LDS_BUILD: largest expected front whose tables the level
+    // kernel builds in LDS itself (0: always a table-build launch)
+    c->lds_build_max = kLevelLdsBuildMax;
+    if (const char *e = getenv("NSGA3_LEVEL_LDS_BUILD")) c->lds_build_max = atoi(e);
     if (const char *e = getenv("NSGA3_HOST_LEVELS")) {
         const int v = atoi(e);
         if (v >= 1 && v <= kMaxHostLevels) c->fixed_levels = v;

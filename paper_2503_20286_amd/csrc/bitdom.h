@@ -154,17 +154,15 @@ __device__ __forceinline__ void block_sync() {
 // (and the header and positions when k0 == 0), so several waves can share one
 // table.
 template <int M, bool kWaveSync = false>
-__device__ __forceinline__ void build_block(const uint32_t *__restrict__ rec, int32_t n,
-                                            uint32_t *__restrict__ tabs, int32_t b, int32_t *inv,
-                                            int k0 = 0, int kstep = 1) {
+__device__ __forceinline__ void build_block_at(const uint32_t *__restrict__ rec, int32_t n,
+                                               uint32_t *T, int32_t b, int32_t *inv, int k0,
+                                               int kstep) {
     constexpr int MP = rec_stride(M);
-    constexpr int TS = blk_stride(M);
     if ((int64_t)b * kBlk >= n) return;
     const int l = (int)lane_id();
     const int32_t e = b * kBlk + l;
     const bool valid = e < n;
     const int32_t nmem = min(kBlk, n - b * kBlk);
-    uint32_t *T = tabs + (size_t)b * TS;
     if (k0 == 0) {
         const int32_t pos = valid ? (int32_t)rec[(size_t)e * MP + M] : 0x7fffffff;
         T[blk_pos_off() + l] = (uint32_t)pos;
@@ -202,6 +200,14 @@ __device__ __forceinline__ void build_block(const uint32_t *__restrict__ rec, in
         }
         block_sync<kWaveSync>();
     }
+}
+
+// Table b of the list in global memory (see build_block_at).
+template <int M, bool kWaveSync = false>
+__device__ __forceinline__ void build_block(const uint32_t *__restrict__ rec, int32_t n,
+                                            uint32_t *__restrict__ tabs, int32_t b, int32_t *inv,
+                                            int k0 = 0, int kstep = 1) {
+    build_block_at<M, kWaveSync>(rec, n, tabs + (size_t)b * blk_stride(M), b, inv, k0, kstep);
 }
 
 // Stage `nb` consecutive tables into LDS.
@@ -358,14 +364,20 @@ __device__ __forceinline__ void fwd_level_item(const uint32_t *__restrict__ tabs
 // while each chunk is staged in LDS in turn, and each point's decrement goes
 // out with one atomic.  A chunk that starts at or after the tile's last run
 // ends the sweep (later chunks start later still).
-template <int M, int TJ>
+// kLds: the chunk's tables are built in LDS from the front's records fk (nf of
+// them) instead of staged from tabs: for small fronts, whose few tables cost
+// less to rebuild per item than a launch of their own.  (A variant of its
+// own: the build code needs far more registers than the probe.)
+template <int M, int TJ, bool kLds>
 __device__ __forceinline__ void fwd_level_group(const uint32_t *__restrict__ tabs, int32_t b0,
                                                 int32_t cb, int32_t ng, int32_t nblk,
                                                 const uint32_t *__restrict__ uk,
                                                 const int32_t *__restrict__ urun, int32_t nu,
                                                 int32_t *__restrict__ ucnt, int32_t jt,
-                                                uint32_t *lt) {
+                                                uint32_t *lt, const uint32_t *__restrict__ fk,
+                                                int32_t nf, int32_t *inv /* [waves][kBlk] */) {
     constexpr int TS = blk_stride(M);
+    constexpr int MP = rec_stride(M);
     constexpr int TILE = kFwdThreads * TJ;
     if (jt * TILE >= nu) return;
     const int32_t last_run = vld(&urun[min((jt + 1) * TILE, nu) - 1]);
@@ -386,10 +398,21 @@ __device__ __forceinline__ void fwd_level_group(const uint32_t *__restrict__ tab
     for (int32_t g = 0; g < ng; ++g) {
         const int32_t bs = b0 + g * cb;
         if (bs >= nblk) break;
-        if ((int32_t)vld(&tabs[(size_t)bs * TS]) >= last_run) break;
+        // sorted position of the chunk's first member
+        const int32_t first = kLds ? (int32_t)vld(&fk[(size_t)bs * kBlk * MP + M])
+                                   : (int32_t)vld(&tabs[(size_t)bs * TS]);
+        if (first >= last_run) break;
         const int32_t nb = min(cb, nblk - bs);
         __syncthreads();  // every wave is done with the previous chunk
-        stage_tables<M>(lt, tabs, bs, nb);
+        if constexpr (kLds) {
+            // one (table, objective) per wave at a time; objective 0 also
+            // writes the table's header and positions
+            for (int job = w; job < nb * M; job += kFwdThreads / kWave)
+                build_block_at<M, true>(fk, nf, lt + (job / M) * TS, bs + job / M,
+                                        inv + w * kBlk, job % M, M);
+        } else {
+            stage_tables<M>(lt, tabs, bs, nb);
+        }
         __syncthreads();
         if (active) fwd_blocks<M, TJ>(lt, nb, run_lo, run_hi, kj, run, cnt);
     }

@@ -167,15 +167,19 @@ constexpr int kLevelTileJ = kFwdThreads * kLevelTJ;
 #endif
 constexpr int kLevelChunksPerItem = NSGA3_LEVEL_CHUNKS;
 
-template <int M>
+// kLds: the front's tables are built in LDS by every item from the front's
+// records fk (no table-build launch for the level).
+template <int M, bool kLds>
 __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
-    const uint32_t *__restrict__ tabs, const uint32_t *__restrict__ uk,
-    const int32_t *__restrict__ urun, int32_t *__restrict__ ucnt, int32_t level,
-    const int32_t *__restrict__ fsize, const int32_t *__restrict__ usize,
-    uint32_t *__restrict__ work, const DevScalars *__restrict__ sc) {
+    const uint32_t *__restrict__ tabs, const uint32_t *__restrict__ fk,
+    const uint32_t *__restrict__ uk, const int32_t *__restrict__ urun,
+    int32_t *__restrict__ ucnt, int32_t level, const int32_t *__restrict__ fsize,
+    const int32_t *__restrict__ usize, uint32_t *__restrict__ work,
+    const DevScalars *__restrict__ sc) {
     constexpr int TS = blk_stride(M);
     constexpr int CB = level_kernel_chunk<M>();
     __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
+    __shared__ int32_t inv[kLds ? kFwdThreads / kWave * kBlk : 1];
     __shared__ int32_t s_item;
     if (sc->err) return;
     const int32_t nf = fsize[level];
@@ -197,7 +201,8 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
     while (item < nitems) {
         const int32_t ig = (int32_t)(item / nJG);
         const int32_t jg = (int32_t)(item % nJG);
-        fwd_level_group<M, kLevelTJ>(tabs, ig * ng * cb, cb, ng, nblk, uk, urun, nu, ucnt, jg, lt);
+        fwd_level_group<M, kLevelTJ, kLds>(tabs, ig * ng * cb, cb, ng, nblk, uk, urun, nu, ucnt,
+                                           jg, lt, fk, nf, inv);
         if (threadIdx.x == 0) s_item = (int32_t)(gridDim.x + atomicAdd(&work[level], 1u));
         __syncthreads();  // every wave is done with lt
         item = s_item;
@@ -503,23 +508,31 @@ hipError_t run_bit_counts(const SortViews &v, hipStream_t s) {
 template <int M>
 static void launch_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk,
                          const int32_t *urun, int32_t *ucnt, int level, unsigned grid,
-                         int32_t f_expect, hipStream_t s) {
+                         int32_t f_expect, bool tables_in_lds, hipStream_t s) {
     const int32_t N = (int32_t)v.N;
     const int32_t nblk_max = (N + kBlk - 1) / kBlk;
-    // the front's size is on the device: size the build grid from the size
-    // expected (the kernel strides over any larger front), else for every point
-    int32_t bgrid = nblk_max;
-    if (f_expect > 0) bgrid = min(nblk_max, (f_expect + kBlk - 1) / kBlk * 5 / 4 + 4);
-    hipLaunchKernelGGL(k_build_blocks<M>, dim3(build_grid(bgrid)), dim3(M * kWave), 0, s, fk, -1,
-                       v.fsize + level, v.tabs_lvl, v.sc);
-    hipLaunchKernelGGL(k_fwd_level<M>, dim3(grid), dim3(kFwdThreads), 0, s, v.tabs_lvl, uk, urun,
-                       ucnt, level, v.fsize, v.usize, v.work, v.sc);
+    if (!tables_in_lds) {
+        // the front's size is on the device: size the build grid from the size
+        // expected (the kernel strides over any larger front), else for every point
+        int32_t bgrid = nblk_max;
+        if (f_expect > 0) bgrid = min(nblk_max, (f_expect + kBlk - 1) / kBlk * 5 / 4 + 4);
+        hipLaunchKernelGGL(k_build_blocks<M>, dim3(build_grid(bgrid)), dim3(M * kWave), 0, s, fk,
+                           -1, v.fsize + level, v.tabs_lvl, v.sc);
+    }
+    if (tables_in_lds)
+        hipLaunchKernelGGL((k_fwd_level<M, true>), dim3(grid), dim3(kFwdThreads), 0, s, v.tabs_lvl,
+                           fk, uk, urun, ucnt, level, v.fsize, v.usize, v.work, v.sc);
+    else
+        hipLaunchKernelGGL((k_fwd_level<M, false>), dim3(grid), dim3(kFwdThreads), 0, s,
+                           v.tabs_lvl, fk, uk, urun, ucnt, level, v.fsize, v.usize, v.work, v.sc);
 }
 
 void run_bit_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk, const int32_t *urun,
-                   int32_t *ucnt, int level, unsigned grid, int32_t f_expect, hipStream_t s) {
+                   int32_t *ucnt, int level, unsigned grid, int32_t f_expect,
+                   bool tables_in_lds, hipStream_t s) {
     switch (v.M) {
-#define NSGA3_CASE(m) case m: launch_level<m>(v, fk, uk, urun, ucnt, level, grid, f_expect, s); break;
+#define NSGA3_CASE(m) \
+    case m: launch_level<m>(v, fk, uk, urun, ucnt, level, grid, f_expect, tables_in_lds, s); break;
         NSGA3_CASE(2) NSGA3_CASE(3) NSGA3_CASE(4) NSGA3_CASE(5) NSGA3_CASE(6) NSGA3_CASE(7)
         NSGA3_CASE(8) NSGA3_CASE(9) NSGA3_CASE(10) NSGA3_CASE(11) NSGA3_CASE(12) NSGA3_CASE(13)
         NSGA3_CASE(14) NSGA3_CASE(15) NSGA3_CASE(16)

@@ -70,6 +70,9 @@ struct LaunchCfg {
     // front sizes per level expected from the previous call (0: unknown);
     // they size launch grids only, every kernel covers any actual size
     int32_t fprev[kProfLevels] = {};
+    // levels whose expected front has at most this many points build their
+    // tables inside the level kernel (0: never)
+    int32_t lds_build_max = 0;
 };
 
 // Points left before a peeling tail at or below which one work-group
@@ -87,8 +90,11 @@ hipError_t run_sort_stage(const SortViews &v, const LaunchCfg &cfg, hipStream_t 
 hipError_t run_bit_counts(const SortViews &v, hipStream_t s);
 // Block tables of all sorted points (tabs_all), as the count stage builds them.
 hipError_t run_build_all_tables(const SortViews &v, hipStream_t s);
+// tables_in_lds: no table-build launch; the level kernel builds the front's
+// tables in LDS per item (for fronts expected to be small).
 void run_bit_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk, const int32_t *urun,
-                   int32_t *ucnt, int level, unsigned grid, int32_t f_expect, hipStream_t s);
+                   int32_t *ucnt, int level, unsigned grid, int32_t f_expect,
+                   bool tables_in_lds, hipStream_t s);
 size_t bit_tables_bytes(int64_t N, int M);
 
 // ---- peel.hip -------------------------------------------------------------

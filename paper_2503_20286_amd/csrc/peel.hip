@@ -568,12 +568,14 @@ static hipError_t launch_peel(const SortViews &v, const LaunchCfg &cfg, hipStrea
                                v.ucnt[p], -1, k, v.fk[q], v.uk[q], v.urun[q], v.ucnt[q], v.rank_s,
                                v.fsize, v.usize, lb_cur, lb_next, v.sc);
         }
-        if (cfg.bitsets)
-            run_bit_level(v, v.fk[q], v.uk[q], v.urun[q], v.ucnt[q], k, ga,
-                          k < kProfLevels ? cfg.fprev[k] : 0, s);
-        else
+        if (cfg.bitsets) {
+            const int32_t fe = k < kProfLevels ? cfg.fprev[k] : 0;
+            run_bit_level(v, v.fk[q], v.uk[q], v.urun[q], v.ucnt[q], k, ga, fe,
+                          fe > 0 && fe <= cfg.lds_build_max, s);
+        } else {
             hipLaunchKernelGGL(k_phase_a<M>, dim3(ga), dim3(kThreads), 0, s, v.fk[q], v.uk[q],
                                v.urun[q], v.ucnt[q], k, v.fsize, v.usize, v.work, v.sc);
+        }
     }
     int32_t k0 = levels;
     uint32_t *fk0 = v.fk[0], *fk1 = v.fk[1], *uk0 = v.uk[0], *uk1 = v.uk[1];
