@@ -52,8 +52,8 @@ enum EStage : int32_t {
 // tables): limits of 4096, 8192, 16384 and 32768 entries took 14.4, 13.9,
 // 13.6 and 13.5 ms per launch on the mixed batch.
 constexpr int kESplitOne = 16 * kESplit;
-constexpr int kETailDefault = 8192;      // default EInst::tail_max
-constexpr int kETailFrontDefault = 1024; // default EInst::tail_front
+constexpr int kETailDefault = 2048;      // default EInst::tail_max
+constexpr int kETailFrontDefault = 256;  // default EInst::tail_front
 
 // Per-instance scalars (in the instance's workspace).
 struct EScal {
