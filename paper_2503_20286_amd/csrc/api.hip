@@ -64,6 +64,7 @@ struct nsga3_ctx {
     int fixed_levels;               // > 0: always enqueue this many peeling levels
     double tail_work;               // peeling work left for the one-work-group tail
     int32_t lds_build_max;          // LaunchCfg::lds_build_max
+    bool wide;                      // LaunchCfg::wide
     volatile int32_t *last_fronts;  // pinned: front count, then level sizes, of the latest call
     std::vector<hipEvent_t> ev_pool;   // NSGA3_NUM_PHASES + 1 events per recorded call
     size_t ev_used;
@@ -113,7 +114,7 @@ Layout layout_for(int64_t N, int M, int H, int max_grid) {
     L.runstart = bump(c, 4 * n);
     L.runend = bump(c, 4 * n);
     L.tabs_all = bump(c, bit_tables_bytes(N, M));
-    L.tabs_lvl = bump(c, bit_tables_bytes(N, M));
+    L.tabs_lvl = bump(c, level_tables_bytes(N, M));
     L.dom_in_s = bump(c, 4 * n);
     L.dom_out_s = bump(c, 4 * n);
     L.rank_s = bump(c, 4 * n);
@@ -232,6 +233,7 @@ LaunchCfg ctx_cfg(const nsga3_ctx *ctx, int M, int64_t N) {
     cfg.bitsets = ctx->bitsets;
     cfg.tail_block = ctx->tail_block;
     cfg.out_mode = ctx->out_mode;
+    cfg.wide = ctx->wide;
     cfg.lds_build_max = ctx->lds_build_max;
     // The previous call's front count and level sizes arrive asynchronously
     // in pinned memory; they only size launches (a stale or torn read shifts
@@ -324,6 +326,7 @@ SortViews sort_views(char *w, const Layout &L, const nsga3_problem &p, int32_t *
     sv.sc = sc;
     sv.bar = WS(GridBar, bar);
     sv.mark = mk;
+    sv.wide = cfg.wide;
     sv.out_mode = cfg.out_mode;
 #undef WS
     return sv;
@@ -561,6 +564,8 @@ nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt)
     // last levels) at or below which those levels go to one work-group
     c->tail_work = kTailPairWork;
     if (const char *e = getenv("NSGA3_TAIL_WORK")) c->tail_work = atof(e);
+    // NSGA3_WIDE_TABLES=0: all-pairs counts with 64-member tables for every M
+    c->wide = !(getenv("NSGA3_WIDE_TABLES") && atoi(getenv("NSGA3_WIDE_TABLES")) == 0);
     // NSGA3_LEVEL_LDS_BUILD: largest expected front whose tables the level
     // kernel builds in LDS itself (0: always a table-build launch)
     c->lds_build_max = kLevelLdsBuildMax;
@@ -741,7 +746,8 @@ nsga3_status nsga3_hype_select(nsga3_ctx *ctx, const float *objs, int64_t N, int
     if (e == hipSuccess && ctx->last_fronts)
         e = hipMemcpyAsync((void *)ctx->last_fronts, &sc->fb[0], sizeof(int32_t) * (1 + kProfLevels),
                            hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess && !cfg.bitsets) e = run_build_all_tables(sv, stream);
+    // the sample probes read 64-member tables of all points
+    if (e == hipSuccess && (!cfg.bitsets || counts_use_wide(sv))) e = run_build_all_tables(sv, stream);
     if (e == hipSuccess) {
         HypeViews hv;
         hv.objs = objs;

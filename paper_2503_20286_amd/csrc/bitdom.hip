@@ -9,6 +9,7 @@
 // i lies before the run of points sharing j's key sum (identical rows and
 // equal-sum points never dominate each other).
 #include "bitdom.h"
+#include "bitdom_wide.h"
 #include "engine.h"
 #include "kernels.h"
 #include "prims.h"
@@ -147,6 +148,120 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_all(const uint32_t *__restr
     if (sc->err) return;
     fwd_all_item<M, kOut>(tabs, nblk, recs, runstart, N, dom_in, dom_out, (int32_t)blockIdx.x,
                           (int32_t)blockIdx.y, lt, oc);
+}
+
+// ---------------------------------------------------------------------------
+// All-pairs counts with wide (128-member) tables, M >= 4: the shape of
+// fwd_all_item with wide chunks (kChunksPerItemWide of them per work-group, so
+// that a work-group covers about as many members as with 64-member tables).
+// ---------------------------------------------------------------------------
+constexpr int kLdsCountWideDwords = 8192;
+constexpr int kChunksPerItemWide = 3;
+template <int M>
+__host__ __device__ constexpr int count_chunk_wide() {
+    return kLdsCountWideDwords / wblk_stride(M) < 1 ? 1 : kLdsCountWideDwords / wblk_stride(M);
+}
+
+template <int M>
+__global__ __launch_bounds__(M * kWave) void k_build_wide(const uint32_t *__restrict__ rec,
+                                                           int32_t n,
+                                                           uint32_t *__restrict__ tabs,
+                                                           const DevScalars *__restrict__ sc) {
+    __shared__ int32_t inv[M][kWBlk];
+    if (sc->err) return;
+    const int32_t nblk = (n + kWBlk - 1) / kWBlk;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    for (int32_t b = (int32_t)blockIdx.x; b < nblk; b += (int32_t)gridDim.x)
+        build_wide_at<M>(rec, n, tabs + (size_t)b * wblk_stride(M), b, inv[w], w, M);
+}
+
+__device__ __forceinline__ void stage_words(uint32_t *lds, const uint32_t *__restrict__ src,
+                                            int32_t nwords) {
+    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+    uint4 *d4 = reinterpret_cast<uint4 *>(lds);
+    for (int q = threadIdx.x; q < nwords / 4; q += kFwdThreads) d4[q] = s4[q];
+}
+
+template <int M, bool kOut>
+__global__ __launch_bounds__(kFwdThreads) void k_fwd_all_wide(
+    const uint32_t *__restrict__ tabs, int32_t nblk, const uint32_t *__restrict__ recs,
+    const int32_t *__restrict__ runstart, int32_t N, int32_t *__restrict__ dom_in,
+    int32_t *__restrict__ dom_out, const DevScalars *__restrict__ sc) {
+    constexpr int CB = count_chunk_wide<M>();
+    constexpr int TS = wblk_stride(M);
+    constexpr int T = kTilesPerItem;
+    __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
+    __shared__ uint32_t oc[kOut ? CB * kWBlk : 1];
+    if (sc->err) return;
+    const int32_t nIC = (nblk + CB - 1) / CB;
+    const int32_t jt0 = (int32_t)blockIdx.x * T;
+    const int32_t c0 = (int32_t)blockIdx.y * kChunksPerItemWide;
+    const int32_t c1 = min(c0 + kChunksPerItemWide, nIC);
+    if (c0 >= nIC) return;
+    const int32_t last_run = runstart[min((jt0 + T) * kTileJ, N) - 1];
+    if (c0 * CB * kWBlk >= last_run) return;  // every chunk starts after every run
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = (int)lane_id();
+    uint32_t kj[T][kTJ][M];
+    int32_t run[T][kTJ], cnt[T][kTJ], run_lo[T], run_hi[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int32_t jbase = (jt0 + t) * kTileJ + w * kWave * kTJ;
+        load_points<M>(recs, runstart, N, jbase, lane, kj[t], run[t]);
+#pragma unroll
+        for (int u = 0; u < kTJ; ++u) cnt[t][u] = 0;
+        const int32_t jb = min(jbase, N - 1);
+        run_lo[t] = __builtin_amdgcn_readfirstlane(runstart[jb]);
+        run_hi[t] = jbase < N ? __builtin_amdgcn_readfirstlane(
+                                    runstart[min(jbase + kWave * kTJ - 1, N - 1)])
+                              : 0;  // no points: no chunk reaches them
+    }
+    if constexpr (kOut)
+        for (int q = threadIdx.x; q < CB * kWBlk; q += kFwdThreads) oc[q] = 0u;
+    int32_t pb0 = -1, pnb = 0;  // chunk whose out-degree counters are pending
+    for (int32_t c = c0; c < c1; ++c) {
+        const int32_t b0 = c * CB;
+        if (b0 * kWBlk >= last_run) break;  // later chunks start later still
+        const int32_t nb = min(CB, nblk - b0);
+        __syncthreads();  // the previous chunk is consumed
+        if constexpr (kOut) {
+            if (pb0 >= 0) {
+                for (int q = threadIdx.x; q < pnb * kWBlk; q += kFwdThreads) {
+                    const uint32_t v = oc[q];
+                    if (v) {
+                        atomicAdd(&dom_out[pb0 * kWBlk + q], (int32_t)v);
+                        oc[q] = 0u;
+                    }
+                }
+            }
+        }
+        stage_words(lt, tabs + (size_t)b0 * TS, nb * TS);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+            if (b0 * kWBlk < run_hi[t])
+                fwd_blocks_wide<M, kTJ, kOut>(lt, nb, run_lo[t], run_hi[t], kj[t], run[t], cnt[t],
+                                              oc);
+        pb0 = b0;
+        pnb = nb;
+    }
+    if constexpr (kOut) {
+        if (pb0 >= 0) {
+            __syncthreads();
+            for (int q = threadIdx.x; q < pnb * kWBlk; q += kFwdThreads) {
+                const uint32_t v = oc[q];
+                if (v) atomicAdd(&dom_out[pb0 * kWBlk + q], (int32_t)v);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+        for (int u = 0; u < kTJ; ++u) {
+            const int32_t q = (jt0 + t) * kTileJ + w * kWave * kTJ + u * kWave + lane;
+            if (q < N && cnt[t][u]) atomicAdd(&dom_in[q], cnt[t][u]);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -448,9 +563,34 @@ bool fused_out_counts(int M, int out_mode) {
     return out_mode == 0 || (out_mode < 0 && M >= kFusedOutMinM);
 }
 
+bool counts_use_wide(const SortViews &v) {
+    return v.wide && wide_counts(v.M) && (!v.dom_out || fused_out_counts(v.M, v.out_mode));
+}
+
 template <int M>
 static hipError_t launch_counts(const SortViews &v, hipStream_t s) {
     const int32_t N = (int32_t)v.N;
+    if constexpr (wide_counts(M)) {
+        if (counts_use_wide(v)) {
+            const int32_t nw = (N + kWBlk - 1) / kWBlk;
+            constexpr int CBW = count_chunk_wide<M>();
+            hipLaunchKernelGGL(k_build_wide<M>, dim3((unsigned)nw), dim3(M * kWave), 0, s, v.recs, N,
+                               v.tabs_all, v.sc);
+            const unsigned nJG = (unsigned)(((N + kTileJ - 1) / kTileJ + kTilesPerItem - 1) /
+                                            kTilesPerItem);
+            const unsigned nCG = (unsigned)(((nw + CBW - 1) / CBW + kChunksPerItemWide - 1) /
+                                            kChunksPerItemWide);
+            if (v.dom_out)
+                hipLaunchKernelGGL((k_fwd_all_wide<M, true>), dim3(nJG, nCG), dim3(kFwdThreads), 0,
+                                   s, v.tabs_all, nw, v.recs, v.runstart, N, v.dom_in_s,
+                                   v.dom_out_s, v.sc);
+            else
+                hipLaunchKernelGGL((k_fwd_all_wide<M, false>), dim3(nJG, nCG), dim3(kFwdThreads), 0,
+                                   s, v.tabs_all, nw, v.recs, v.runstart, N, v.dom_in_s,
+                                   v.dom_out_s, v.sc);
+            return hipGetLastError();
+        }
+    }
     const int32_t nblk = (N + kBlk - 1) / kBlk;
     constexpr int CB = count_chunk<M>();
     hipLaunchKernelGGL(k_build_blocks<M>, dim3(build_grid(nblk)), dim3(M * kWave), 0, s, v.recs, N,
@@ -541,8 +681,14 @@ void run_bit_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk, c
     }
 }
 
-size_t bit_tables_bytes(int64_t N, int M) {
+size_t level_tables_bytes(int64_t N, int M) {
     return (size_t)((N + kBlk - 1) / kBlk) * (size_t)blk_stride(M) * sizeof(uint32_t);
+}
+
+size_t bit_tables_bytes(int64_t N, int M) {
+    const size_t narrow = (size_t)((N + kBlk - 1) / kBlk) * (size_t)blk_stride(M);
+    const size_t wide = (size_t)((N + kWBlk - 1) / kWBlk) * (size_t)wblk_stride(M);
+    return (narrow > wide ? narrow : wide) * sizeof(uint32_t);
 }
 
 }  // namespace nsga3

@@ -51,6 +51,7 @@ struct SortViews {
     uint32_t *blkcnt;            // [2 * max grid] per-block counts
     int32_t *rank, *dom_in, *dom_out;  // outputs in original order (dom_* may be null)
     int out_mode = -1;                 // as LaunchCfg::out_mode
+    bool wide = true;                  // all-pairs counts with 128-member tables (M >= 4)
     DevScalars *sc;
     GridBar *bar;                // grid-barrier state (zeroed per call)
     Marker mark;
@@ -67,6 +68,7 @@ struct LaunchCfg {
     bool tail_block;            // single-workgroup peeling tail (graph capture)
     int out_mode = -1;          // out-degrees: -1 by objective count, 0 from the in-degree
                                 // pass, 1 by their own backward pass
+    bool wide = true;           // 128-member tables for the all-pairs counts (M >= 4)
     // front sizes per level expected from the previous call (0: unknown);
     // they size launch grids only, every kernel covers any actual size
     int32_t fprev[kProfLevels] = {};
@@ -90,12 +92,16 @@ hipError_t run_sort_stage(const SortViews &v, const LaunchCfg &cfg, hipStream_t 
 hipError_t run_bit_counts(const SortViews &v, hipStream_t s);
 // Block tables of all sorted points (tabs_all), as the count stage builds them.
 hipError_t run_build_all_tables(const SortViews &v, hipStream_t s);
+// Whether the count stage of v builds 128-member tables in tabs_all (which the
+// 64-member probes of later stages cannot read).
+bool counts_use_wide(const SortViews &v);
 // tables_in_lds: no table-build launch; the level kernel builds the front's
 // tables in LDS per item (for fronts expected to be small).
 void run_bit_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk, const int32_t *urun,
                    int32_t *ucnt, int level, unsigned grid, int32_t f_expect,
                    bool tables_in_lds, hipStream_t s);
-size_t bit_tables_bytes(int64_t N, int M);
+size_t bit_tables_bytes(int64_t N, int M);    // all points: 64- or 128-member tables
+size_t level_tables_bytes(int64_t N, int M);  // a front's 64-member tables
 
 // ---- peel.hip -------------------------------------------------------------
 hipError_t run_peel(const SortViews &v, const LaunchCfg &cfg, hipStream_t s);

@@ -381,6 +381,33 @@ def test_out_degree_forms_parity(separate, monkeypatch):
     ctx.close()
 
 
+@pytest.mark.parametrize("wide", ["0", "1"])
+def test_wide_table_counts_parity(wide, monkeypatch):
+    """All-pairs counts with 128-member tables (NSGA3_WIDE_TABLES=1, the
+    default for 4 <= M <= 10) and with 64-member tables (=0) give the oracle's
+    counts and ranks: every M of the wide range, ragged sizes around the
+    128-member blocks (1, 127, 128, 129, 2,049), ties and duplicates, with and
+    without the count outputs."""
+    import paper_2503_20286_amd as nsga3
+    monkeypatch.setenv("NSGA3_WIDE_TABLES", wide)
+    ctx = nsga3.Context(0)
+    monkeypatch.delenv("NSGA3_WIDE_TABLES")
+    rng = np.random.default_rng(41)
+    for M in (4, 5, 6, 7, 8, 9, 10, 11):
+        for N in (1, 127, 128, 129, 2049):
+            F = rng.integers(0, 6, size=(N, M)).astype(np.float32)  # ties and duplicates
+            R = np.abs(rng.standard_normal((20, M))).astype(np.float32) + 0.05
+            K = max(1, N // 2)
+            print(f"wide={wide} M={M} N={N}", flush=True)
+            g = gpu_select(F, R, K, ctx=ctx)
+            _zero(compare_full(F, R, K, g))
+    w = workloads.make("large", N=6000, seed=44)
+    g = gpu_select(w.objs, w.refs, w.K, ctx=ctx, want_counts=False)
+    s = oracle.select(w.objs, w.refs, w.K, with_counts=False)
+    assert np.array_equal(g["rank"], s.rank)
+    ctx.close()
+
+
 @pytest.mark.parametrize("tail_block,levels", [(True, 2), (False, 1), (True, 5)])
 def test_peeling_tails(tail_block, levels, monkeypatch):
     """Levels beyond the enqueued ones are finished by the cooperative tail or
