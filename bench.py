@@ -624,8 +624,10 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "dominance counts (k_build_blocks + k_fwd_all: block bitsets; out-degrees from "
-                      "the in-degree probes for M >= 4, a backward pass k_bwd_all below)",
+            "kernel": "dominance counts (block bitsets: k_build_wide + k_fwd_all_wide, 128-member "
+                      "tables, for 4 <= M <= 10; k_build_blocks + k_fwd_all, 64-member tables, "
+                      "otherwise; out-degrees from the in-degree probes for M >= 4, a backward pass "
+                      "k_bwd_all below)",
             "achieved": achieved,
             "peak": peak,
             "unit": "Tcmp/s",
@@ -633,8 +635,8 @@ def main():
             "traffic": traffic,
             "work_per_launch": f"{cmp_per_launch:.4e} pair-objective compares (M*N*(N-1)/2: every "
                                "unordered pair decided once)",
-            "note": "effective pair-decision rate: one block-bitset probe decides 64 pairs with "
-                    "M key searches and M mask ANDs, so frac is not a VALU utilisation and can "
+            "note": "effective pair-decision rate: one block-bitset probe decides 64 or 128 pairs "
+                    "with M key searches and M mask ANDs, so frac is not a VALU utilisation and can "
                     "exceed 1",
             "frac_counts_and_peeling": cmp_per_launch / ((phases["dominance_count"] + phases["peel"])
                                                           / 1e3) / PEAK_CMP_PER_S,
