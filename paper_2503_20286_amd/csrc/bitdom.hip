@@ -151,12 +151,13 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_all(const uint32_t *__restr
 }
 
 // ---------------------------------------------------------------------------
-// All-pairs counts with wide (128-member) tables, M >= 4: the shape of
-// fwd_all_item with wide chunks (kChunksPerItemWide of them per work-group, so
-// that a work-group covers about as many members as with 64-member tables).
+// All-pairs counts with wide (128-member) tables, 4 <= M <= 10: the shape of
+// fwd_all_item with wide chunks of two tables, two chunks per work-group (N =
+// 200k, M = 5, both counts: 1.229 ms; three chunks 1.250, four 1.272; chunks
+// of one table, six per item 1.272; of three tables, two per item 1.406).
 // ---------------------------------------------------------------------------
 constexpr int kLdsCountWideDwords = 8192;
-constexpr int kChunksPerItemWide = 3;
+constexpr int kChunksPerItemWide = 2;
 template <int M>
 __host__ __device__ constexpr int count_chunk_wide() {
     return kLdsCountWideDwords / wblk_stride(M) < 1 ? 1 : kLdsCountWideDwords / wblk_stride(M);
