@@ -152,12 +152,14 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_all(const uint32_t *__restr
 
 // ---------------------------------------------------------------------------
 // All-pairs counts with wide (128-member) tables, 4 <= M <= 10: the shape of
-// fwd_all_item with wide chunks of two tables, two chunks per work-group (N =
-// 200k, M = 5, both counts: 1.229 ms; three chunks 1.250, four 1.272; chunks
-// of one table, six per item 1.272; of three tables, two per item 1.406).
+// fwd_all_item with a chunk of two wide tables and two point tiles per
+// work-group (N = 200k, M = 5, both counts: 1.212 ms; two chunks 1.229, three
+// 1.250, four 1.272; one tile and two or four chunks 1.29; three tiles and two
+// chunks 1.23; chunks of one table, six per item 1.272; of three, two 1.406).
 // ---------------------------------------------------------------------------
 constexpr int kLdsCountWideDwords = 8192;
-constexpr int kChunksPerItemWide = 2;
+constexpr int kChunksPerItemWide = 1;
+constexpr int kTilesPerItemWide = 2;
 template <int M>
 __host__ __device__ constexpr int count_chunk_wide() {
     return kLdsCountWideDwords / wblk_stride(M) < 1 ? 1 : kLdsCountWideDwords / wblk_stride(M);
@@ -190,7 +192,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_all_wide(
     int32_t *__restrict__ dom_out, const DevScalars *__restrict__ sc) {
     constexpr int CB = count_chunk_wide<M>();
     constexpr int TS = wblk_stride(M);
-    constexpr int T = kTilesPerItem;
+    constexpr int T = kTilesPerItemWide;
     __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
     __shared__ uint32_t oc[kOut ? CB * kWBlk : 1];
     if (sc->err) return;
@@ -577,8 +579,8 @@ static hipError_t launch_counts(const SortViews &v, hipStream_t s) {
             constexpr int CBW = count_chunk_wide<M>();
             hipLaunchKernelGGL(k_build_wide<M>, dim3((unsigned)nw), dim3(M * kWave), 0, s, v.recs, N,
                                v.tabs_all, v.sc);
-            const unsigned nJG = (unsigned)(((N + kTileJ - 1) / kTileJ + kTilesPerItem - 1) /
-                                            kTilesPerItem);
+            const unsigned nJG = (unsigned)(((N + kTileJ - 1) / kTileJ + kTilesPerItemWide - 1) /
+                                            kTilesPerItemWide);
             const unsigned nCG = (unsigned)(((nw + CBW - 1) / CBW + kChunksPerItemWide - 1) /
                                             kChunksPerItemWide);
             if (v.dom_out)
