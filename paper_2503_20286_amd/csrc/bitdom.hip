@@ -165,13 +165,16 @@ __host__ __device__ constexpr int count_chunk_wide() {
     return kLdsCountWideDwords / wblk_stride(M) < 1 ? 1 : kLdsCountWideDwords / wblk_stride(M);
 }
 
+// Wide tables of a list of n records (n_static, or *n_dev when n_static < 0).
 template <int M>
 __global__ __launch_bounds__(M * kWave) void k_build_wide(const uint32_t *__restrict__ rec,
-                                                           int32_t n,
+                                                           int32_t n_static,
+                                                           const int32_t *__restrict__ n_dev,
                                                            uint32_t *__restrict__ tabs,
                                                            const DevScalars *__restrict__ sc) {
     __shared__ int32_t inv[M][kWBlk];
     if (sc->err) return;
+    const int32_t n = n_static >= 0 ? n_static : *n_dev;
     const int32_t nblk = (n + kWBlk - 1) / kWBlk;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     for (int32_t b = (int32_t)blockIdx.x; b < nblk; b += (int32_t)gridDim.x)
@@ -321,6 +324,51 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_level(
         const int32_t jg = (int32_t)(item % nJG);
         fwd_level_group<M, kLevelTJ, kLds>(tabs, ig * ng * cb, cb, ng, nblk, uk, urun, nu, ucnt,
                                            jg, lt, fk, nf, inv);
+        if (threadIdx.x == 0) s_item = (int32_t)(gridDim.x + atomicAdd(&work[level], 1u));
+        __syncthreads();  // every wave is done with lt
+        item = s_item;
+        __syncthreads();
+    }
+}
+
+// Decrements of one level against wide (128-member) tables of the front: the
+// loop of k_fwd_level with wide chunks (two tables; 27 KiB of LDS at M = 5).
+constexpr int kLdsLevelWideDwords = 6864;
+constexpr int kLevelTJWide = 2;  // points per lane (three need 109 VGPRs)
+constexpr int kLevelTileJWide = kFwdThreads * kLevelTJWide;
+template <int M>
+__host__ __device__ constexpr int level_wide_chunk() {
+    return kLdsLevelWideDwords / wblk_stride(M) < 1 ? 1 : kLdsLevelWideDwords / wblk_stride(M);
+}
+
+template <int M>
+__global__ __launch_bounds__(kFwdThreads) void k_fwd_level_wide(
+    const uint32_t *__restrict__ tabs, const uint32_t *__restrict__ uk,
+    const int32_t *__restrict__ urun, int32_t *__restrict__ ucnt, int32_t level,
+    const int32_t *__restrict__ fsize, const int32_t *__restrict__ usize,
+    uint32_t *__restrict__ work, const DevScalars *__restrict__ sc) {
+    constexpr int TS = wblk_stride(M);
+    constexpr int CB = level_wide_chunk<M>();
+    __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
+    __shared__ int32_t s_item;
+    if (sc->err) return;
+    const int32_t nf = fsize[level];
+    const int32_t nu = usize[level];
+    if (nf == 0 || nu == 0) return;
+    const int32_t nblk = (nf + kWBlk - 1) / kWBlk;
+    const int32_t nJG = (nu + kLevelTileJWide - 1) / kLevelTileJWide;
+    int32_t cb = CB;
+    while (cb > 1 && (int64_t)((nblk + cb / 2 - 1) / (cb / 2)) * nJG <= (int64_t)gridDim.x) cb >>= 1;
+    const int32_t nIC = (nblk + cb - 1) / cb;
+    int32_t ng = kLevelChunksPerItem;
+    while (ng > 1 && (int64_t)((nIC + ng - 1) / ng) * nJG < 2 * (int64_t)gridDim.x) ng >>= 1;
+    const int64_t nitems = (int64_t)((nIC + ng - 1) / ng) * nJG;
+    int64_t item = blockIdx.x;
+    while (item < nitems) {
+        const int32_t ig = (int32_t)(item / nJG);
+        const int32_t jg = (int32_t)(item % nJG);
+        fwd_level_group_wide<M, kLevelTJWide>(tabs, ig * ng * cb, cb, ng, nblk, uk, urun, nu, ucnt, jg,
+                                          lt);
         if (threadIdx.x == 0) s_item = (int32_t)(gridDim.x + atomicAdd(&work[level], 1u));
         __syncthreads();  // every wave is done with lt
         item = s_item;
@@ -578,7 +626,7 @@ static hipError_t launch_counts(const SortViews &v, hipStream_t s) {
             const int32_t nw = (N + kWBlk - 1) / kWBlk;
             constexpr int CBW = count_chunk_wide<M>();
             hipLaunchKernelGGL(k_build_wide<M>, dim3((unsigned)nw), dim3(M * kWave), 0, s, v.recs, N,
-                               v.tabs_all, v.sc);
+                               (const int32_t *)nullptr, v.tabs_all, v.sc);
             const unsigned nJG = (unsigned)(((N + kTileJ - 1) / kTileJ + kTilesPerItemWide - 1) /
                                             kTilesPerItemWide);
             const unsigned nCG = (unsigned)(((nw + CBW - 1) / CBW + kChunksPerItemWide - 1) /
@@ -653,6 +701,18 @@ static void launch_level(const SortViews &v, const uint32_t *fk, const uint32_t 
                          const int32_t *urun, int32_t *ucnt, int level, unsigned grid,
                          int32_t f_expect, bool tables_in_lds, hipStream_t s) {
     const int32_t N = (int32_t)v.N;
+    if constexpr (wide_counts(M)) {
+        if (!tables_in_lds && v.wide_levels) {
+            const int32_t nw_max = (N + kWBlk - 1) / kWBlk;
+            int32_t bgrid = nw_max;
+            if (f_expect > 0) bgrid = min(nw_max, (f_expect + kWBlk - 1) / kWBlk * 5 / 4 + 4);
+            hipLaunchKernelGGL(k_build_wide<M>, dim3((unsigned)bgrid), dim3(M * kWave), 0, s, fk, -1,
+                               v.fsize + level, v.tabs_lvl, v.sc);
+            hipLaunchKernelGGL(k_fwd_level_wide<M>, dim3(grid), dim3(kFwdThreads), 0, s, v.tabs_lvl,
+                               uk, urun, ucnt, level, v.fsize, v.usize, v.work, v.sc);
+            return;
+        }
+    }
     const int32_t nblk_max = (N + kBlk - 1) / kBlk;
     if (!tables_in_lds) {
         // the front's size is on the device: size the build grid from the size
@@ -684,9 +744,7 @@ void run_bit_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk, c
     }
 }
 
-size_t level_tables_bytes(int64_t N, int M) {
-    return (size_t)((N + kBlk - 1) / kBlk) * (size_t)blk_stride(M) * sizeof(uint32_t);
-}
+size_t level_tables_bytes(int64_t N, int M) { return bit_tables_bytes(N, M); }
 
 size_t bit_tables_bytes(int64_t N, int M) {
     const size_t narrow = (size_t)((N + kBlk - 1) / kBlk) * (size_t)blk_stride(M);

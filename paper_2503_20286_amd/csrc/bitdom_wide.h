@@ -249,4 +249,61 @@ __device__ __forceinline__ void fwd_blocks_wide(const uint32_t *lt, int32_t nb, 
     }
 }
 
+// Stage nb consecutive wide tables into LDS.
+template <int M>
+__device__ __forceinline__ void stage_wide(uint32_t *lds, const uint32_t *__restrict__ tabs,
+                                           int32_t b0, int32_t nb) {
+    constexpr int TS = wblk_stride(M);
+    const uint4 *src = reinterpret_cast<const uint4 *>(tabs + (size_t)b0 * TS);
+    uint4 *dst = reinterpret_cast<uint4 *>(lds);
+    for (int q = threadIdx.x; q < nb * (TS / 4); q += kFwdThreads) dst[q] = src[q];
+}
+
+// fwd_level_group with wide tables of the front: one tile of kFwdThreads * TJ
+// remaining points (keys in registers) against ng consecutive chunks of cb
+// wide tables from table b0 on, one atomic per point.
+template <int M, int TJ>
+__device__ __forceinline__ void fwd_level_group_wide(const uint32_t *__restrict__ tabs,
+                                                     int32_t b0, int32_t cb, int32_t ng,
+                                                     int32_t nblk, const uint32_t *__restrict__ uk,
+                                                     const int32_t *__restrict__ urun, int32_t nu,
+                                                     int32_t *__restrict__ ucnt, int32_t jt,
+                                                     uint32_t *lt) {
+    constexpr int TS = wblk_stride(M);
+    constexpr int TILE = kFwdThreads * TJ;
+    if (jt * TILE >= nu) return;
+    const int32_t last_run = vld(&urun[min((jt + 1) * TILE, nu) - 1]);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = (int)lane_id();
+    const int32_t jbase = jt * TILE + w * kWave * TJ;
+    const bool active = jbase < nu;  // uniform in the wave
+    uint32_t kj[TJ][M];
+    int32_t run[TJ], cnt[TJ];
+    int32_t run_lo = 0, run_hi = 0;
+#pragma unroll
+    for (int u = 0; u < TJ; ++u) cnt[u] = 0;
+    if (active) {
+        load_points<M, TJ>(uk, urun, nu, jbase, lane, kj, run);
+        run_lo = vld(&urun[jbase]);
+        run_hi = vld(&urun[min(jbase + kWave * TJ - 1, nu - 1)]);
+    }
+    for (int32_t g = 0; g < ng; ++g) {
+        const int32_t bs = b0 + g * cb;
+        if (bs >= nblk) break;
+        if ((int32_t)vld(&tabs[(size_t)bs * TS]) >= last_run) break;
+        const int32_t nb = min(cb, nblk - bs);
+        __syncthreads();  // every wave is done with the previous chunk
+        stage_wide<M>(lt, tabs, bs, nb);
+        __syncthreads();
+        if (active) fwd_blocks_wide<M, TJ, false>(lt, nb, run_lo, run_hi, kj, run, cnt, nullptr);
+    }
+    if (active) {
+#pragma unroll
+        for (int u = 0; u < TJ; ++u) {
+            const int32_t q = jbase + u * kWave + lane;
+            if (q < nu && cnt[u]) atomicSub(&ucnt[q], cnt[u]);
+        }
+    }
+}
+
 }  // namespace nsga3

@@ -52,6 +52,7 @@ struct SortViews {
     int32_t *rank, *dom_in, *dom_out;  // outputs in original order (dom_* may be null)
     int out_mode = -1;                 // as LaunchCfg::out_mode
     bool wide = true;                  // all-pairs counts with 128-member tables (M >= 4)
+    bool wide_levels = false;          // peeling levels with 128-member front tables
     DevScalars *sc;
     GridBar *bar;                // grid-barrier state (zeroed per call)
     Marker mark;
@@ -69,6 +70,7 @@ struct LaunchCfg {
     int out_mode = -1;          // out-degrees: -1 by objective count, 0 from the in-degree
                                 // pass, 1 by their own backward pass
     bool wide = true;           // 128-member tables for the all-pairs counts (M >= 4)
+    bool wide_levels = false;   // 128-member front tables for the staged peeling levels
     // front sizes per level expected from the previous call (0: unknown);
     // they size launch grids only, every kernel covers any actual size
     int32_t fprev[kProfLevels] = {};
@@ -101,7 +103,7 @@ void run_bit_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk, c
                    int32_t *ucnt, int level, unsigned grid, int32_t f_expect,
                    bool tables_in_lds, hipStream_t s);
 size_t bit_tables_bytes(int64_t N, int M);    // all points: 64- or 128-member tables
-size_t level_tables_bytes(int64_t N, int M);  // a front's 64-member tables
+size_t level_tables_bytes(int64_t N, int M);  // a front's 64- or 128-member tables
 
 // ---- peel.hip -------------------------------------------------------------
 hipError_t run_peel(const SortViews &v, const LaunchCfg &cfg, hipStream_t s);

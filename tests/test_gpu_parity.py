@@ -384,14 +384,17 @@ def test_out_degree_forms_parity(separate, monkeypatch):
 @pytest.mark.parametrize("wide", ["0", "1"])
 def test_wide_table_counts_parity(wide, monkeypatch):
     """All-pairs counts with 128-member tables (NSGA3_WIDE_TABLES=1, the
-    default for 4 <= M <= 10) and with 64-member tables (=0) give the oracle's
-    counts and ranks: every M of the wide range, ragged sizes around the
-    128-member blocks (1, 127, 128, 129, 2,049), ties and duplicates, with and
-    without the count outputs."""
+    default for 4 <= M <= 10) and with 64-member tables (=0), and peeling
+    levels with 128-member front tables (NSGA3_WIDE_LEVELS=1, opt-in) or
+    64-member ones, give the oracle's counts and ranks: every M of the wide
+    range, ragged sizes around the 128-member blocks (1, 127, 128, 129, 2,049),
+    ties and duplicates, with and without the count outputs."""
     import paper_2503_20286_amd as nsga3
     monkeypatch.setenv("NSGA3_WIDE_TABLES", wide)
+    monkeypatch.setenv("NSGA3_WIDE_LEVELS", wide)
     ctx = nsga3.Context(0)
     monkeypatch.delenv("NSGA3_WIDE_TABLES")
+    monkeypatch.delenv("NSGA3_WIDE_LEVELS")
     rng = np.random.default_rng(41)
     for M in (4, 5, 6, 7, 8, 9, 10, 11):
         for N in (1, 127, 128, 129, 2049):
