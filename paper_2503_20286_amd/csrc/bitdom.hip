@@ -706,9 +706,11 @@ static void launch_level(const SortViews &v, const uint32_t *fk, const uint32_t 
             const int32_t nw_max = (N + kWBlk - 1) / kWBlk;
             int32_t bgrid = nw_max;
             if (f_expect > 0) bgrid = min(nw_max, (f_expect + kWBlk - 1) / kWBlk * 5 / 4 + 4);
+            // the wide front tables go to the all-points table space, which the
+            // counts no longer need (tabs_lvl is sized for 64-member tables)
             hipLaunchKernelGGL(k_build_wide<M>, dim3((unsigned)bgrid), dim3(M * kWave), 0, s, fk, -1,
-                               v.fsize + level, v.tabs_lvl, v.sc);
-            hipLaunchKernelGGL(k_fwd_level_wide<M>, dim3(grid), dim3(kFwdThreads), 0, s, v.tabs_lvl,
+                               v.fsize + level, v.tabs_all, v.sc);
+            hipLaunchKernelGGL(k_fwd_level_wide<M>, dim3(grid), dim3(kFwdThreads), 0, s, v.tabs_all,
                                uk, urun, ucnt, level, v.fsize, v.usize, v.work, v.sc);
             return;
         }
@@ -744,7 +746,9 @@ void run_bit_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk, c
     }
 }
 
-size_t level_tables_bytes(int64_t N, int M) { return bit_tables_bytes(N, M); }
+size_t level_tables_bytes(int64_t N, int M) {
+    return (size_t)((N + kBlk - 1) / kBlk) * (size_t)blk_stride(M) * sizeof(uint32_t);
+}
 
 size_t bit_tables_bytes(int64_t N, int M) {
     const size_t narrow = (size_t)((N + kBlk - 1) / kBlk) * (size_t)blk_stride(M);

@@ -103,7 +103,7 @@ void run_bit_level(const SortViews &v, const uint32_t *fk, const uint32_t *uk, c
                    int32_t *ucnt, int level, unsigned grid, int32_t f_expect,
                    bool tables_in_lds, hipStream_t s);
 size_t bit_tables_bytes(int64_t N, int M);    // all points: 64- or 128-member tables
-size_t level_tables_bytes(int64_t N, int M);  // a front's 64- or 128-member tables
+size_t level_tables_bytes(int64_t N, int M);  // a front's 64-member tables
 
 // ---- peel.hip -------------------------------------------------------------
 hipError_t run_peel(const SortViews &v, const LaunchCfg &cfg, hipStream_t s);
