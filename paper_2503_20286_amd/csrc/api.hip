@@ -1138,19 +1138,22 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
     // phase-3 engine holds the CUs: behind the chain they ran starved beside
     // two engines (4.9 ms instead of 0.3).  512-instance batch: 11.1-11.2 ms
     // per launch against 11.5-11.7 with them chained last (mode 1); all
-    // counts together (mode 0) 11.4 ms.  NSGA3_PLAN_COUNT_ORDER selects.
+    // counts together (mode 0) 11.4 ms; mode 3 chains the M >= 3 classes in
+    // descending M instead (11.7 ms).  NSGA3_PLAN_COUNT_ORDER selects.
     const bool overlap = !(getenv("NSGA3_PLAN_OVERLAP") && atoi(getenv("NSGA3_PLAN_OVERLAP")) == 0);
     int order_mode = 2;
     if (const char *oe = getenv("NSGA3_PLAN_COUNT_ORDER")) order_mode = atoi(oe);
     const bool ordered = order_mode != 0;
     // mode 2: the two-objective classes' counts start right after their own
     // phase 1, beside the other classes' chain instead of after it
-    const bool m2_free = order_mode == 2;
+    const bool m2_free = order_mode >= 2;
     std::vector<int> corder(nclass);
     for (int c = 0; c < nclass; ++c) corder[c] = c;
+    const bool descending = order_mode == 3;  // mode 3: as 2, M >= 3 classes in descending M
     std::stable_sort(corder.begin(), corder.end(), [&](int x, int y) {
         const int mx = inst[cls[x].first].M, my = inst[cls[y].first].M;
-        return std::make_pair(mx == 2, mx) < std::make_pair(my == 2, my);
+        return std::make_pair(mx == 2, descending ? -mx : mx) <
+               std::make_pair(my == 2, descending ? -my : my);
     });
     hipEvent_t *cev = ev + 2 * nclass + 2;  // counts of class c done
     // phase 1 (branch per class): keys, presort, records; parked before the counts
