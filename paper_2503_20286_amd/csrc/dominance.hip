@@ -79,24 +79,38 @@ __global__ __launch_bounds__(kThreads) void k_build_recs(const float *__restrict
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const uint32_t i = sval[p];
-    for (int k = 0; k < MP; ++k) {
-        uint32_t v = 0;
-        if (k < M) v = order_key(objs[(int64_t)i * M + k]);
-        else if (k == M) v = (uint32_t)p;
-        recs[p * MP + k] = v;
+    // the record in 16-byte stores (MP is a multiple of 4): whole lines reach
+    // the L2 instead of one dword per lane 32 bytes apart
+    uint4 *dst = reinterpret_cast<uint4 *>(recs + p * MP);
+    for (int q = 0; q < MP / 4; ++q) {
+        uint32_t v[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = 4 * q + t;
+            v[t] = k < M ? order_key(objs[(int64_t)i * M + k]) : (k == M ? (uint32_t)p : 0u);
+        }
+        dst[q] = make_uint4(v[0], v[1], v[2], v[3]);
     }
+    // run bounds: most key sums are unique, so the neighbours usually settle
+    // them; a binary search only inside a run of equal sums
     const uint64_t me = skey[p];
-    int64_t lo = 0, hi = p;  // first q in [0, p] with skey[q] == me
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (skey[mid] < me) lo = mid + 1; else hi = mid;
+    int64_t lo = p, hi;
+    if (p > 0 && skey[p - 1] == me) {
+        lo = 0;  // first q in [0, p] with skey[q] == me
+        hi = p;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (skey[mid] < me) lo = mid + 1; else hi = mid;
+        }
     }
     runstart[p] = (int32_t)lo;
     lo = p + 1;  // first q > p with a larger key sum
-    hi = N;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (skey[mid] <= me) lo = mid + 1; else hi = mid;
+    if (p + 1 < N && skey[p + 1] == me) {
+        hi = N;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (skey[mid] <= me) lo = mid + 1; else hi = mid;
+        }
     }
     runend[p] = (int32_t)lo;
 }
