@@ -108,11 +108,12 @@ __device__ __forceinline__ uint64_t low_bits(uint32_t c) {
 constexpr int kFwdThreads = 256;
 constexpr int kTJ = 2;                            // points per lane
 constexpr int kTileJ = kFwdThreads * kTJ;         // points per work item
-// Tables staged per work-group: the all-pairs counts take 24.5 KiB chunks (six
-// M = 5 tables; with the out-degree counters six work-groups stay resident per
-// CU: 2.98 ms for both counts at N = 200k, M = 5 when they were separate
-// passes, against 3.24 ms with 34 KiB and 3.81 ms with 49 KiB); a peeling
-// level's items take 34 KiB (1.77 ms for the peel, against 1.82 ms with 24 KiB).
+// Tables staged per work-group: the 64-member all-pairs counts take 24.5 KiB
+// chunks (six M = 5 tables; with the out-degree counters six work-groups stay
+// resident per CU: 2.98 ms for both counts at N = 200k, M = 5 when they were
+// separate passes, against 3.24 ms with 34 KiB and 3.81 ms with 49 KiB); the
+// batched engine's peeling items take 34 KiB (kLdsLevelDwords), the single
+// call's level kernel 24 KiB (kLdsLevelKernelDwords, below).
 #ifndef NSGA3_LDS_COUNT_DWORDS
 #define NSGA3_LDS_COUNT_DWORDS 6264
 #endif
@@ -223,11 +224,10 @@ __device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__re
 
 // Forward: for each of the wave's kTJ x 64 points j (keys kj, run starts run),
 // add the number of members of the staged blocks that dominate j.  With kOut,
-// every dominating member also gains one in its LDS counter (member q = b * 64
-// + bit of the staged chunk: the 16-bit half q & 1 of oc[q >> 1]; a work-group
-// adds at most kTilesPerItem * kTileJ < 65536 to one member per chunk): the
-// same probes then give the out-degrees of the staged members, since every
-// dominance pair (i before j's run) is probed exactly once.
+// every dominating member also gains one in its 32-bit LDS counter oc[q]
+// (member q = b * 64 + bit of the staged chunk): the same probes then give the
+// out-degrees of the staged members, since every dominance pair (i before j's
+// run) is probed exactly once.
 template <int M, int TJ = kTJ, bool kOut = false>
 __device__ __forceinline__ void fwd_blocks(const uint32_t *lt, int32_t nb, int32_t run_lo,
                                            int32_t run_hi, const uint32_t (&kj)[TJ][M],

@@ -48,10 +48,10 @@ inline unsigned build_grid(int64_t nblk) { return (unsigned)nblk; }
 // (1, 2) 2.92, (2, 1) 2.86, (2, 4) 2.93, (3, 2) 2.89, (4, 1) 2.97, (4, 3) 3.06.
 constexpr int kTilesPerItem = 2;
 constexpr int kChunksPerItem = 2;
-static_assert(kTilesPerItem * kTileJ < 65536, "16-bit out-degree counters per chunk");
 
-// LDS out-degree counters of one staged chunk (two 16-bit counters per
-// dword) -> global (sorted positions b0 * 64 + member), cleared for the next
+
+// LDS out-degree counters of one staged chunk (one 32-bit counter per
+// member) -> global (sorted positions b0 * 64 + member), cleared for the next
 // chunk.
 __device__ __forceinline__ void flush_out_counts(uint32_t *oc, int32_t b0, int32_t nb,
                                                  int32_t *__restrict__ dom_out) {
@@ -64,9 +64,9 @@ __device__ __forceinline__ void flush_out_counts(uint32_t *oc, int32_t b0, int32
     }
 }
 
-// kOut: out-degrees of the chunk members from the same probes (LDS counters
-// oc[count_chunk * 32], two per dword; one global atomic per non-zero counter
-// per chunk).
+// kOut: out-degrees of the chunk members from the same probes (32-bit LDS
+// counters oc[count_chunk * 64]; one global atomic per non-zero counter per
+// chunk).
 template <int M, bool kOut>
 __device__ __forceinline__ void fwd_all_item(const uint32_t *__restrict__ tabs, int32_t nblk,
                                              const uint32_t *__restrict__ recs,
@@ -277,7 +277,8 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_all_wide(
 // ---------------------------------------------------------------------------
 constexpr int kFwdLevelTiles = 1;  // remaining-list tiles per item (2 and 4 measured slower)
 // Points per lane of the level kernel: 3 took the peel at N = 200k, M = 5 from
-// 1.64 to 1.57 ms (the all-pairs counts keep kTJ = 2, their best).
+// 1.64 to 1.57 ms when it was measured (the all-pairs counts keep kTJ = 2,
+// their best).
 constexpr int kLevelTJ = 3;
 constexpr int kLevelTileJ = kFwdThreads * kLevelTJ;
 // Chunks of front tables a level work item sweeps for its tile (fewer on
