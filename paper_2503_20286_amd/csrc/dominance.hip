@@ -1,6 +1,7 @@
 // Nondominated sorting on gfx950: prepare order keys, presort by the exact key
-// sum, count dominance over every unordered pair once, then peel the fronts in
-// one persistent cooperative kernel.
+// sum and count dominance over every unordered pair once (block bitsets, in
+// bitdom.hip); the fronts are then peeled level by level (peel.hip), one split
+// and one probe launch per level, with a one-work-group tail for the last ones.
 //
 // Pareto dominance follows Listing 1 / Eq. (6) (minimisation): i dominates j
 // iff f_i <= f_j in every objective and f_i != f_j.  The dominance count of
