@@ -66,6 +66,7 @@ struct nsga3_ctx {
     int32_t lds_build_max;          // LaunchCfg::lds_build_max
     bool wide;                      // LaunchCfg::wide
     bool wide_levels;               // LaunchCfg::wide_levels
+    bool engine_wide;               // batched counts over 128-member tables
     volatile int32_t *last_fronts;  // pinned: front count, then level sizes, of the latest call
     std::vector<hipEvent_t> ev_pool;   // NSGA3_NUM_PHASES + 1 events per recorded call
     size_t ev_used;
@@ -574,6 +575,12 @@ nsga3_status nsga3_create(nsga3_ctx **out, int device, const nsga3_options *opt)
     // 1.30 ms against 1.09 (a wide table build per level, half the members per
     // item, five work-groups per CU instead of six).
     c->wide_levels = getenv("NSGA3_WIDE_LEVELS") && atoi(getenv("NSGA3_WIDE_LEVELS")) != 0;
+    // NSGA3_ENGINE_WIDE=1: batched plans count over 128-member tables too
+    // (4 <= M <= 10, unless NSGA3_WIDE_TABLES=0).  Off by default: beside the
+    // other classes' engines the M = 5 counts of the 512-instance batch took
+    // 2.83 ms against 2.68 (and the table builds 0.64 against 0.51).
+    c->engine_wide = c->wide && getenv("NSGA3_ENGINE_WIDE") &&
+                     atoi(getenv("NSGA3_ENGINE_WIDE")) != 0;
     // NSGA3_LEVEL_LDS_BUILD: largest expected front whose tables the level
     // kernel builds in LDS itself (0: always a table-build launch)
     c->lds_build_max = kLevelLdsBuildMax;
@@ -865,7 +872,8 @@ static nsga3_status tune_group(nsga3_ctx *ctx, const std::vector<nsga3::EInst> &
     std::vector<int2> map, cmap;  // block-table builds, count work-groups
     for (int32_t q = 0; q < nb; ++q) {
         int64_t nbld = 0, ncnt = 0;
-        engine_bitdom_items(group[q].N, group[q].M, &nbld, &ncnt);
+        engine_bitdom_items(group[q].N, group[q].M, ctx->out_mode, ctx->engine_wide, &nbld,
+                            &ncnt);
         for (int64_t t = 0; t < nbld; ++t) map.push_back(make_int2(q, (int)t));
         for (int64_t t = 0; t < ncnt; ++t) cmap.push_back(make_int2(q, (int)t));
     }
@@ -913,7 +921,7 @@ static nsga3_status tune_group(nsga3_ctx *ctx, const std::vector<nsga3::EInst> &
             if (e == hipSuccess) e = engine_launch(M, d_inst, d_state, 0, nb, d_glob, nullptr, kSDom, grid, s);
             if (e == hipSuccess)
                 e = engine_bitdom_launch(M, d_inst, d_state, d_map, (int64_t)nmap, d_map + nmap,
-                                         (int64_t)cmap.size(), ctx->out_mode, s);
+                                         (int64_t)cmap.size(), ctx->out_mode, ctx->engine_wide, s);
             if (e == hipSuccess) e = engine_resume(d_inst, d_state, 0, nb, d_glob + 1, s);
             if (e == hipSuccess) e = engine_launch(M, d_inst, d_state, 0, nb, d_glob + 1, nullptr, kSDone, grid, s);
             if (e == hipSuccess) e = hipEventRecord(e1, s);
@@ -1029,7 +1037,8 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
         coff[c] = (int64_t)cmap.size();
         for (int32_t q = cls[c].first; q < cls[c].first + cls[c].second; ++q) {
             int64_t nbld = 0, ncnt = 0;
-            engine_bitdom_items(inst[q].N, inst[q].M, &nbld, &ncnt);
+            engine_bitdom_items(inst[q].N, inst[q].M, ctx->out_mode, ctx->engine_wide, &nbld,
+                                &ncnt);
             for (int64_t t = 0; t < nbld; ++t) bmap.push_back(make_int2(q, (int)t));
             for (int64_t t = 0; t < ncnt; ++t) cmap.push_back(make_int2(q, (int)t));
         }
@@ -1125,7 +1134,7 @@ static nsga3_status plan_create_engine(nsga3_ctx *ctx, const nsga3_problem *prob
         if (pl->bitdom)
             return engine_bitdom_launch(M, pl->d_inst, pl->d_state, pl->d_bmap + boff[c],
                                         boff[c + 1] - boff[c], pl->d_cmap + coff[c],
-                                        coff[c + 1] - coff[c], ctx->out_mode, st);
+                                        coff[c + 1] - coff[c], ctx->out_mode, ctx->engine_wide, st);
         return engine_dom_launch(M, pl->d_inst, pl->d_state, pl->d_map + map_off[c],
                                  map_off[c + 1] - map_off[c], st);
     };

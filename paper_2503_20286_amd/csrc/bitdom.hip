@@ -188,20 +188,20 @@ __device__ __forceinline__ void stage_words(uint32_t *lds, const uint32_t *__res
     for (int q = threadIdx.x; q < nwords / 4; q += kFwdThreads) d4[q] = s4[q];
 }
 
+// One work item of the all-pairs counts over wide tables: kTilesPerItemWide
+// tiles of points (group jg) against kChunksPerItemWide chunks of tables
+// (group cg).  lt holds a chunk of tables, oc its out-degree counters.
 template <int M, bool kOut>
-__global__ __launch_bounds__(kFwdThreads) void k_fwd_all_wide(
+__device__ __forceinline__ void fwd_all_wide_item(
     const uint32_t *__restrict__ tabs, int32_t nblk, const uint32_t *__restrict__ recs,
     const int32_t *__restrict__ runstart, int32_t N, int32_t *__restrict__ dom_in,
-    int32_t *__restrict__ dom_out, const DevScalars *__restrict__ sc) {
+    int32_t *__restrict__ dom_out, int32_t jg, int32_t cg, uint32_t *lt, uint32_t *oc) {
     constexpr int CB = count_chunk_wide<M>();
     constexpr int TS = wblk_stride(M);
     constexpr int T = kTilesPerItemWide;
-    __shared__ __attribute__((aligned(16))) uint32_t lt[CB * TS];
-    __shared__ uint32_t oc[kOut ? CB * kWBlk : 1];
-    if (sc->err) return;
     const int32_t nIC = (nblk + CB - 1) / CB;
-    const int32_t jt0 = (int32_t)blockIdx.x * T;
-    const int32_t c0 = (int32_t)blockIdx.y * kChunksPerItemWide;
+    const int32_t jt0 = jg * T;
+    const int32_t c0 = cg * kChunksPerItemWide;
     const int32_t c1 = min(c0 + kChunksPerItemWide, nIC);
     if (c0 >= nIC) return;
     const int32_t last_run = runstart[min((jt0 + T) * kTileJ, N) - 1];
@@ -268,6 +268,18 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_all_wide(
             if (q < N && cnt[t][u]) atomicAdd(&dom_in[q], cnt[t][u]);
         }
     }
+}
+
+template <int M, bool kOut>
+__global__ __launch_bounds__(kFwdThreads) void k_fwd_all_wide(
+    const uint32_t *__restrict__ tabs, int32_t nblk, const uint32_t *__restrict__ recs,
+    const int32_t *__restrict__ runstart, int32_t N, int32_t *__restrict__ dom_in,
+    int32_t *__restrict__ dom_out, const DevScalars *__restrict__ sc) {
+    __shared__ __attribute__((aligned(16))) uint32_t lt[count_chunk_wide<M>() * wblk_stride(M)];
+    __shared__ uint32_t oc[kOut ? count_chunk_wide<M>() * kWBlk : 1];
+    if (sc->err) return;
+    fwd_all_wide_item<M, kOut>(tabs, nblk, recs, runstart, N, dom_in, dom_out, (int32_t)blockIdx.x,
+                               (int32_t)blockIdx.y, lt, oc);
 }
 
 // ---------------------------------------------------------------------------
@@ -513,15 +525,18 @@ __device__ __forceinline__ T *inst_at(const EInst &I, size_t off) {
     return reinterpret_cast<T *>(I.ws + off);
 }
 
+// One table per work-group, one wave per objective (as k_build_blocks).
 template <int M>
-__global__ __launch_bounds__(64) void k_eng_build(const EInst *__restrict__ inst,
-                                                  const EState *__restrict__ st,
-                                                  const int2 *__restrict__ map) {
-    __shared__ int32_t inv[kBlk];
+__global__ __launch_bounds__(M * kWave) void k_eng_build(const EInst *__restrict__ inst,
+                                                         const EState *__restrict__ st,
+                                                         const int2 *__restrict__ map) {
+    __shared__ int32_t inv[M][kBlk];
     const int2 e = map[blockIdx.x];
     if (st[e.x].stage != kSDom) return;
     const EInst &I = inst[e.x];
-    build_block<M>(inst_at<const uint32_t>(I, I.L.recs), I.N, inst_at<uint32_t>(I, I.L.tabs), e.y, inv);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    build_block<M, true>(inst_at<const uint32_t>(I, I.L.recs), I.N, inst_at<uint32_t>(I, I.L.tabs),
+                         e.y, inv[w], w, M);
 }
 
 // kWhat: 0 in-degrees, 1 out-degrees (backward pass), 2 both from one pass.
@@ -550,12 +565,60 @@ __global__ __launch_bounds__(kFwdThreads) void k_eng_count(const EInst *__restri
                                     cg, lt, oc);
 }
 
+// Wide-table form (both counts from one pass), for the objective counts the
+// single-selection counts also run on wide tables.
+template <int M>
+__global__ __launch_bounds__(M * kWave) void k_eng_build_wide(const EInst *__restrict__ inst,
+                                                              const EState *__restrict__ st,
+                                                              const int2 *__restrict__ map) {
+    __shared__ int32_t inv[M][kWBlk];
+    const int2 e = map[blockIdx.x];
+    if (st[e.x].stage != kSDom) return;
+    const EInst &I = inst[e.x];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    build_wide_at<M>(inst_at<const uint32_t>(I, I.L.recs), I.N,
+                     inst_at<uint32_t>(I, I.L.tabs) + (size_t)e.y * wblk_stride(M), e.y, inv[w], w,
+                     M);
+}
+
+template <int M>
+__global__ __launch_bounds__(kFwdThreads) void k_eng_count_wide(const EInst *__restrict__ inst,
+                                                                const EState *__restrict__ st,
+                                                                const int2 *__restrict__ map) {
+    constexpr int CB = count_chunk_wide<M>();
+    __shared__ __attribute__((aligned(16))) uint32_t lt[CB * wblk_stride(M)];
+    __shared__ uint32_t oc[CB * kWBlk];
+    const int2 e = map[blockIdx.x];
+    if (st[e.x].stage != kSDom) return;
+    const EInst &I = inst[e.x];
+    const int32_t N = I.N;
+    const int32_t nw = (N + kWBlk - 1) / kWBlk;
+    const int32_t nCG = ((nw + CB - 1) / CB + kChunksPerItemWide - 1) / kChunksPerItemWide;
+    fwd_all_wide_item<M, true>(inst_at<const uint32_t>(I, I.L.tabs), nw,
+                               inst_at<const uint32_t>(I, I.L.recs),
+                               inst_at<const int32_t>(I, I.L.runstart), N,
+                               inst_at<int32_t>(I, I.L.din), inst_at<int32_t>(I, I.L.dout),
+                               e.y / nCG, e.y % nCG, lt, oc);
+}
+
 template <int M>
 static hipError_t launch_eng_bitdom(const EInst *inst, const EState *st, const int2 *bmap,
                                     int64_t nb_build, const int2 *cmap, int64_t nb_count,
-                                    bool fused, hipStream_t s) {
+                                    bool fused, bool wide, hipStream_t s) {
+    if constexpr (wide_counts(M)) {
+        if (wide) {
+            if (nb_build > 0)
+                hipLaunchKernelGGL(k_eng_build_wide<M>, dim3((unsigned)nb_build), dim3(M * kWave),
+                                   0, s, inst, st, bmap);
+            if (nb_count > 0)
+                hipLaunchKernelGGL(k_eng_count_wide<M>, dim3((unsigned)nb_count),
+                                   dim3(kFwdThreads), 0, s, inst, st, cmap);
+            return hipGetLastError();
+        }
+    }
     if (nb_build > 0)
-        hipLaunchKernelGGL(k_eng_build<M>, dim3((unsigned)nb_build), dim3(64), 0, s, inst, st, bmap);
+        hipLaunchKernelGGL(k_eng_build<M>, dim3((unsigned)nb_build), dim3(M * kWave), 0, s, inst, st,
+                           bmap);
     if (nb_count > 0) {
         if (fused) {  // in-degrees and out-degrees from one pass
             hipLaunchKernelGGL((k_eng_count<M, 2>), dim3((unsigned)nb_count), dim3(kFwdThreads), 0,
@@ -570,12 +633,17 @@ static hipError_t launch_eng_bitdom(const EInst *inst, const EState *st, const i
     return hipGetLastError();
 }
 
+bool engine_counts_wide(int M, int out_mode, bool wide) {
+    return wide && wide_counts(M) && fused_out_counts(M, out_mode);
+}
+
 hipError_t engine_bitdom_launch(int M, const EInst *inst, const EState *st, const int2 *bmap,
                                 int64_t nb_build, const int2 *cmap, int64_t nb_count,
-                                int out_mode, hipStream_t s) {
+                                int out_mode, bool wide, hipStream_t s) {
     const bool fused = fused_out_counts(M, out_mode);
+    wide = engine_counts_wide(M, out_mode, wide);
     switch (M) {
-#define NSGA3_CASE(m) case m: return launch_eng_bitdom<m>(inst, st, bmap, nb_build, cmap, nb_count, fused, s);
+#define NSGA3_CASE(m) case m: return launch_eng_bitdom<m>(inst, st, bmap, nb_build, cmap, nb_count, fused, wide, s);
         NSGA3_CASE(2) NSGA3_CASE(3) NSGA3_CASE(4) NSGA3_CASE(5) NSGA3_CASE(6) NSGA3_CASE(7)
         NSGA3_CASE(8) NSGA3_CASE(9) NSGA3_CASE(10) NSGA3_CASE(11) NSGA3_CASE(12) NSGA3_CASE(13)
         NSGA3_CASE(14) NSGA3_CASE(15) NSGA3_CASE(16)
@@ -584,7 +652,23 @@ hipError_t engine_bitdom_launch(int M, const EInst *inst, const EState *st, cons
     }
 }
 
-void engine_bitdom_items(int64_t N, int M, int64_t *n_build, int64_t *n_count) {
+void engine_bitdom_items(int64_t N, int M, int out_mode, bool wide, int64_t *n_build,
+                         int64_t *n_count) {
+    if (engine_counts_wide(M, out_mode, wide)) {
+        int cbw = 1;
+        switch (M) {
+#define NSGA3_CB(m) case m: cbw = count_chunk_wide<m>(); break;
+            NSGA3_CB(4) NSGA3_CB(5) NSGA3_CB(6) NSGA3_CB(7) NSGA3_CB(8) NSGA3_CB(9) NSGA3_CB(10)
+#undef NSGA3_CB
+            default: break;
+        }
+        const int64_t nw = (N + kWBlk - 1) / kWBlk;
+        const int64_t nJG = ((N + kTileJ - 1) / kTileJ + kTilesPerItemWide - 1) / kTilesPerItemWide;
+        const int64_t nCG = ((nw + cbw - 1) / cbw + kChunksPerItemWide - 1) / kChunksPerItemWide;
+        *n_build = nw;
+        *n_count = nJG * nCG;
+        return;
+    }
     int cb = 1;
     switch (M) {
 #define NSGA3_CB(m) case m: cb = count_chunk<m>(); break;

@@ -35,6 +35,8 @@ __host__ __device__ constexpr int wblk_mask(int k, int q, int c) {
            (c - 32 * (c < 128 ? c >> 5 : 3));
 }
 __host__ __device__ constexpr int wblk_stride(int M) { return (wblk_obj_off(M) + 3) / 4 * 4; }
+static_assert(wblk_stride(4) == wide_blk_stride(4) && wblk_stride(10) == wide_blk_stride(10),
+              "workspace sizing and the wide table layout disagree");
 
 // Objective counts that count with wide tables: from M = 4 on the out-degrees
 // come from the in-degree probes, and the probe is the cost; above M = 10 the

@@ -85,4 +85,8 @@ struct Ws;  // workspace views, defined in the runtime
 // masks, laid out in bitdom.h), rounded to whole 16-byte vectors.
 __host__ __device__ constexpr int blk_stride(int M) { return ((68 + 195 * M) + 3) / 4 * 4; }
 
+// Dwords of one 128-member (wide) table (header and positions, then 660 dwords
+// per objective, laid out in bitdom_wide.h), rounded to whole 16-byte vectors.
+__host__ __device__ constexpr int wide_blk_stride(int M) { return ((132 + 660 * M) + 3) / 4 * 4; }
+
 }  // namespace nsga3

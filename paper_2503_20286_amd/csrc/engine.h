@@ -97,7 +97,11 @@ __host__ __device__ inline ELayout elayout(int64_t N, int M, int H) {
     L.recs = bump(4 * n * MP);
     L.runstart = bump(4 * n);
     L.runend = bump(4 * n);
-    L.tabs = bump(4 * (size_t)cdiv(N, 64) * (size_t)blk_stride(M));
+    // 64-member tables (counts, peeling levels) or, for 4 <= M <= 10, the
+    // larger 128-member tables of the counts
+    const size_t tab_narrow = (size_t)cdiv(N, 64) * (size_t)blk_stride(M);
+    const size_t tab_wide = (M >= 4 && M <= 10) ? (size_t)cdiv(N, 128) * (size_t)wide_blk_stride(M) : 0;
+    L.tabs = bump(4 * (tab_narrow > tab_wide ? tab_narrow : tab_wide));
     L.din = bump(4 * n);
     L.dout = bump(4 * n);
     L.rank_s = bump(4 * n);
@@ -190,12 +194,17 @@ hipError_t engine_resume(const EInst *inst, EState *st, int32_t b0, int32_t nb, 
 // Block-bitset dominance counts of every parked instance (bitdom.hip): block
 // tables (bmap[q] = (instance, block), nb_build entries), then in-degrees and
 // out-degrees (cmap[q] = (instance, work-group), nb_count entries).
-// out_mode as LaunchCfg::out_mode.
+// out_mode as LaunchCfg::out_mode; wide allows 128-member tables where the
+// single-selection counts use them (engine_counts_wide).
 hipError_t engine_bitdom_launch(int M, const EInst *inst, const EState *st, const int2 *bmap,
                                 int64_t nb_build, const int2 *cmap, int64_t nb_count,
-                                int out_mode, hipStream_t s);
-// Block tables and count work-groups of one instance for the launch above.
-void engine_bitdom_items(int64_t N, int M, int64_t *n_build, int64_t *n_count);
+                                int out_mode, bool wide, hipStream_t s);
+// Block tables and count work-groups of one instance for the launch above
+// (same M, out_mode and wide).
+void engine_bitdom_items(int64_t N, int M, int out_mode, bool wide, int64_t *n_build,
+                         int64_t *n_count);
+// Whether the launch above counts over 128-member tables.
+bool engine_counts_wide(int M, int out_mode, bool wide);
 
 // Number of dominance items of an instance of N points.
 inline int64_t engine_dom_items(int64_t N) {

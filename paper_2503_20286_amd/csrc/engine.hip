@@ -67,6 +67,15 @@ __device__ __forceinline__ void copy_rec(uint32_t *d, const uint32_t *s) {
         reinterpret_cast<uint4 *>(d)[k] = reinterpret_cast<const uint4 *>(s)[k];
 }
 
+// Dword c of a 16-byte vector.
+template <int c>
+__device__ __forceinline__ uint32_t vec_dword(const uint4 &v) {
+    if constexpr (c == 0) return v.x;
+    else if constexpr (c == 1) return v.y;
+    else if constexpr (c == 2) return v.z;
+    else return v.w;
+}
+
 // Cooperative copy of n records (MP dwords each) into LDS.
 template <int MP>
 __device__ __forceinline__ void stage_recs(uint32_t *lds, const uint32_t *src, int32_t n) {
@@ -427,21 +436,38 @@ __device__ void item_splitc(const EInst &I, int32_t k, int32_t n, int32_t t,
 
 // Ordered split of list entries [e0, e1) (at most kESplit) into F_k (rank k)
 // and U_k at output offsets (of, ou); each thread owns kESplit / kEThreads
-// consecutive entries and one packed block scan gives every offset.  Returns
-// the chunk's front and remaining counts.
+// consecutive entries and one packed block scan gives every offset.  Every
+// load of a thread's entries (counts, run starts, records) is issued before
+// its first store: the destination lists never overlap the source list, and a
+// worker block has one wave per SIMD, so loads interleaved with the stores
+// would cost one memory round trip per entry.  Returns the chunk's front and
+// remaining counts.
 template <int M>
 __device__ void split_chunk(const LevelLists &s, int32_t k, int32_t e0, int32_t e1, uint32_t of,
                             uint32_t ou, int32_t *rank_s, uint32_t *lds, uint32_t *nf,
                             uint32_t *nu) {
     constexpr int MP = rec_stride(M);
+    constexpr int MV = MP / 4;
     constexpr int kPer = kESplit / kEThreads;
     const int32_t t0 = e0 + (int32_t)threadIdx.x * kPer;
-    int32_t cnt[kPer];
+    int32_t cnt[kPer], run[kPer];
+    uint4 rec[kPer][MV];
     uint32_t zf = 0, zu = 0;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         const int32_t e = t0 + q;
-        cnt[q] = e < e1 ? s.scnt[e] : -1;
+        if (e < e1) {
+            cnt[q] = s.scnt[e];
+            run[q] = s.srun[e];
+            const uint4 *r = reinterpret_cast<const uint4 *>(s.srec + (size_t)e * MP);
+#pragma unroll
+            for (int v = 0; v < MV; ++v) rec[q][v] = r[v];
+        } else {
+            cnt[q] = -1;
+            run[q] = 0;
+#pragma unroll
+            for (int v = 0; v < MV; ++v) rec[q][v] = make_uint4(0u, 0u, 0u, 0u);
+        }
         zf += cnt[q] == 0 ? 1u : 0u;
         zu += (e < e1 && cnt[q] != 0) ? 1u : 0u;
     }
@@ -452,14 +478,17 @@ __device__ void split_chunk(const LevelLists &s, int32_t k, int32_t e0, int32_t 
     for (int q = 0; q < kPer; ++q) {
         const int32_t e = t0 + q;
         if (e >= e1) break;
-        const uint32_t *r = s.srec + (size_t)e * MP;
         if (cnt[q] == 0) {
-            copy_rec<MP>(s.fdst + (size_t)f * MP, r);
-            rank_s[r[M]] = k;
+            uint4 *d = reinterpret_cast<uint4 *>(s.fdst + (size_t)f * MP);
+#pragma unroll
+            for (int v = 0; v < MV; ++v) d[v] = rec[q][v];
+            rank_s[vec_dword<M % 4>(rec[q][M / 4])] = k;
             ++f;
         } else {
-            copy_rec<MP>(s.udst + (size_t)u * MP, r);
-            s.rdst[u] = s.srun[e];
+            uint4 *d = reinterpret_cast<uint4 *>(s.udst + (size_t)u * MP);
+#pragma unroll
+            for (int v = 0; v < MV; ++v) d[v] = rec[q][v];
+            s.rdst[u] = run[q];
             s.cdst[u] = cnt[q];
             ++u;
         }

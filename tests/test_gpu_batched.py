@@ -333,3 +333,36 @@ def test_engine_out_degree_forms_match(separate, monkeypatch):
     _check_against_single(plan, probs, ("out", separate))
     plan.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("wide", ["0", "1"])
+def test_engine_wide_table_counts_match_oracle(wide, monkeypatch):
+    """Batched counts over 128-member tables (NSGA3_ENGINE_WIDE=1, opt-in, for
+    4 <= M <= 10) and over 64-member tables (the default) give the oracle's
+    outputs: every M of the wide range and one beyond it, sizes around the
+    128-member blocks (1, 127, 128, 129, 2,049), ties and duplicates."""
+    import torch
+    import paper_2503_20286_amd as nsga3
+    monkeypatch.setenv("NSGA3_ENGINE_WIDE", wide)
+    ctx = nsga3.Context(0)
+    monkeypatch.delenv("NSGA3_ENGINE_WIDE")
+    rng = np.random.default_rng(43)
+    cases = []
+    for M in (4, 5, 6, 7, 8, 9, 10, 11):
+        for N in (1, 127, 128, 129, 2049):
+            F = rng.integers(0, 6, size=(N, M)).astype(np.float32)  # ties and duplicates
+            R = np.abs(rng.standard_normal((20, M))).astype(np.float32) + 0.05
+            cases.append((F, R, max(1, N // 2)))
+    probs = [(torch.from_numpy(F).cuda(), torch.from_numpy(R).cuda(), K) for F, R, K in cases]
+    print(f"wide={wide}: {len(cases)} instances", flush=True)
+    plan = nsga3.Plan(probs, ctx=ctx)
+    for rep in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        for b, (F, R, K) in enumerate(cases):
+            g = _host(plan.results[b])
+            g["info"] = plan.results[b].info()
+            bad = {k: v for k, v in compare_full(F, R, K, g).items() if k != "near_ties" and v}
+            assert not bad, (wide, rep, b, F.shape, bad)
+    plan.close()
+    ctx.close()
