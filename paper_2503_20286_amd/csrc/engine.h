@@ -13,7 +13,7 @@ namespace nsga3 {
 constexpr int kEThreads = 256;
 constexpr int kEChunk = 1024;      // points per item of the O(N) stages
 constexpr int kERsTile = 2048;     // keys per radix-sort item
-constexpr int kESplit = 2048;      // list entries per split item
+constexpr int kESplit = 512;       // list entries per split item
 constexpr int kECmp = 2048;        // flags per compaction item
 constexpr int kESmem = 12288;      // LDS dwords per worker block
 // Presort key: the exact key sum (at most 36 bits for M <= 16, at most five
@@ -51,7 +51,7 @@ enum EStage : int32_t {
 // Lists up to this length split in one item (which also builds the front's
 // tables): limits of 4096, 8192, 16384 and 32768 entries took 14.4, 13.9,
 // 13.6 and 13.5 ms per launch on the mixed batch.
-constexpr int kESplitOne = 16 * kESplit;
+constexpr int kESplitOne = 64 * kESplit;
 constexpr int kETailDefault = 2048;      // default EInst::tail_max
 constexpr int kETailFrontDefault = 256;  // default EInst::tail_front
 

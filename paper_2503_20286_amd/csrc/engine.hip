@@ -435,13 +435,18 @@ __device__ void item_splitc(const EInst &I, int32_t k, int32_t n, int32_t t,
 }
 
 // Ordered split of list entries [e0, e1) (at most kESplit) into F_k (rank k)
-// and U_k at output offsets (of, ou); each thread owns kESplit / kEThreads
-// consecutive entries and one packed block scan gives every offset.  Every
-// load of a thread's entries (counts, run starts, records) is issued before
-// its first store: the destination lists never overlap the source list, and a
-// worker block has one wave per SIMD, so loads interleaved with the stores
-// would cost one memory round trip per entry.  Returns the chunk's front and
-// remaining counts.
+// and U_k at output offsets (of, ou).  Entry e0 + q * kEThreads + t belongs
+// to thread t, so every load and store instruction covers consecutive
+// entries.  All loads of a thread (counts, run starts, records) are issued
+// before its first store: the destination lists never overlap the source
+// list, and a worker block has one wave per SIMD, so loads interleaved with
+// the stores would cost a memory round trip each.  Offsets: a ballot per
+// (q, wave) gives the fronts before an entry inside its wave; the waves'
+// counts go through LDS once.  Returns the chunk's front and remaining counts.
+// On the 512-instance batch (ms per launch), consecutive entries per thread
+// and one packed block scan: 8 entries with loads and stores interleaved
+// 11.1-11.2; with every load first, 16, 8, 4, 2 and 1 entries 11.7, 11.0,
+// 10.7, 10.5 and 10.4; this form with 8, 2 or 1 entries 10.6, 10.4, 10.4.
 template <int M>
 __device__ void split_chunk(const LevelLists &s, int32_t k, int32_t e0, int32_t e1, uint32_t of,
                             uint32_t ou, int32_t *rank_s, uint32_t *lds, uint32_t *nf,
@@ -449,13 +454,14 @@ __device__ void split_chunk(const LevelLists &s, int32_t k, int32_t e0, int32_t 
     constexpr int MP = rec_stride(M);
     constexpr int MV = MP / 4;
     constexpr int kPer = kESplit / kEThreads;
-    const int32_t t0 = e0 + (int32_t)threadIdx.x * kPer;
+    constexpr int kEW = kEThreads / kWave;
+    const int lane = (int)lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     int32_t cnt[kPer], run[kPer];
     uint4 rec[kPer][MV];
-    uint32_t zf = 0, zu = 0;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-        const int32_t e = t0 + q;
+        const int32_t e = e0 + q * kEThreads + (int32_t)threadIdx.x;
         if (e < e1) {
             cnt[q] = s.scnt[e];
             run[q] = s.srun[e];
@@ -468,33 +474,48 @@ __device__ void split_chunk(const LevelLists &s, int32_t k, int32_t e0, int32_t 
 #pragma unroll
             for (int v = 0; v < MV; ++v) rec[q][v] = make_uint4(0u, 0u, 0u, 0u);
         }
-        zf += cnt[q] == 0 ? 1u : 0u;
-        zu += (e < e1 && cnt[q] != 0) ? 1u : 0u;
     }
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan((zf << 16) | zu, lds, &tot);
-    uint32_t f = of + (ex >> 16), u = ou + (ex & 0xffffu);
+    uint64_t fm[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-        const int32_t e = t0 + q;
-        if (e >= e1) break;
+        fm[q] = ballot(cnt[q] == 0);
+        if (lane == 0) lds[q * kEW + wv] = (uint32_t)__popcll(fm[q]);
+    }
+    __syncthreads();
+    uint32_t before[kPer], tf = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        uint32_t b = tf;
+#pragma unroll
+        for (int x = 0; x < kEW; ++x) {
+            const uint32_t c = lds[q * kEW + x];
+            b += x < wv ? c : 0u;
+            tf += c;
+        }
+        before[q] = b + lanes_below(fm[q]);
+    }
+    __syncthreads();  // lds is free for the next chunk
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int32_t idx = q * kEThreads + (int32_t)threadIdx.x;  // entries before, in the chunk
+        if (e0 + idx >= e1) break;
         if (cnt[q] == 0) {
+            const uint32_t f = of + before[q];
             uint4 *d = reinterpret_cast<uint4 *>(s.fdst + (size_t)f * MP);
 #pragma unroll
             for (int v = 0; v < MV; ++v) d[v] = rec[q][v];
             rank_s[vec_dword<M % 4>(rec[q][M / 4])] = k;
-            ++f;
         } else {
+            const uint32_t u = ou + (uint32_t)idx - before[q];
             uint4 *d = reinterpret_cast<uint4 *>(s.udst + (size_t)u * MP);
 #pragma unroll
             for (int v = 0; v < MV; ++v) d[v] = rec[q][v];
             s.rdst[u] = run[q];
             s.cdst[u] = cnt[q];
-            ++u;
         }
     }
-    *nf = tot >> 16;
-    *nu = tot & 0xffffu;
+    *nf = tf;
+    *nu = (uint32_t)(e1 - e0) - tf;
 }
 
 // Split, writing pass of one item, at the offsets the counting pass scanned.
