@@ -366,3 +366,30 @@ def test_engine_wide_table_counts_match_oracle(wide, monkeypatch):
             assert not bad, (wide, rep, b, F.shape, bad)
     plan.close()
     ctx.close()
+
+
+def test_engine_split_chunk_boundaries():
+    """Level lists whose lengths sit on and around the engine split's
+    512-entry chunks (one-item splits), and one list just over the one-item
+    limit of 32,768 entries (two-stage splits in 512-entry items): every
+    output equals single calls, and the small instances equal the oracle."""
+    import torch
+    import paper_2503_20286_amd as nsga3
+    sizes = [(511, 3), (512, 3), (513, 5), (1023, 5), (1025, 3), (2049, 5), (32769, 3)]
+    ws = [workloads.make_instance(9100 + i, N, M) for i, (N, M) in enumerate(sizes)]
+    probs = _dev(ws)
+    print("sizes", sizes, flush=True)
+    plan = nsga3.Plan(probs)
+    for rep in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        _check_against_single(plan, probs, ("split", rep))
+    for b, w in enumerate(ws):
+        if w.N > 4096:
+            continue
+        g = _host(plan.results[b])
+        g["info"] = plan.results[b].info()
+        bad = {k: v for k, v in compare_full(w.objs, w.refs, w.K, g).items()
+               if k != "near_ties" and v}
+        assert not bad, (b, w.N, w.M, bad)
+    plan.close()
