@@ -555,7 +555,7 @@ __device__ void split_chunk(const LevelLists &s, int32_t k, int32_t e0, int32_t 
         }
     }
     *nf = tf;
-    *nu = (uint32_t)(e1 - e0) - tf;
+    *nu = (uint32_t)max(e1 - e0, 0) - tf;
 }
 
 // Split, writing pass of one item, at the offsets the counting pass scanned.
