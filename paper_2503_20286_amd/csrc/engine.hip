@@ -844,9 +844,11 @@ __device__ void item_build_f(const EInst &I, int32_t k, int32_t t, uint32_t *sme
 // a2, block-bitset form: one (chunk of cb front tables, group of remaining
 // tiles) item of level k; p0 = cb, p1 = tile groups.  Remaining-list tiles per
 // item (whole table chunks per item): 1, 2, 4 and 8 tiles took 18.1, 14.4,
-// 14.1 and 15.2 ms per launch on the mixed batch, and splitting small levels
-// into smaller chunks was slower still.
-constexpr int kLevelTiles = 4;
+// 14.1 and 15.2 ms per launch on the mixed batch when first measured, and
+// splitting small levels into smaller chunks was slower still; with the
+// coalesced level split, 2, 4 and 8 tiles took 10.7-10.8, 10.35-10.41 and
+// 10.24-10.31 ms.
+constexpr int kLevelTiles = 8;
 static_assert(kEThreads == kFwdThreads, "engine work-groups run the bitset bodies");
 
 template <int M>
