@@ -846,8 +846,8 @@ __device__ void item_build_f(const EInst &I, int32_t k, int32_t t, uint32_t *sme
 // item (whole table chunks per item): 1, 2, 4 and 8 tiles took 18.1, 14.4,
 // 14.1 and 15.2 ms per launch on the mixed batch when first measured, and
 // splitting small levels into smaller chunks was slower still; with the
-// coalesced level split, 2, 4 and 8 tiles took 10.7-10.8, 10.35-10.41 and
-// 10.24-10.31 ms.
+// coalesced level split, 2, 4, 8 and 16 tiles took 10.7-10.8, 10.35-10.41,
+// 10.24-10.36 and 10.34-10.56 ms.
 constexpr int kLevelTiles = 8;
 static_assert(kEThreads == kFwdThreads, "engine work-groups run the bitset bodies");
 
